@@ -1,0 +1,199 @@
+/*
+ * hodbf.h -- C ABI of an MI355X (gfx950) library for the butterfly-accelerated
+ * volume integral equation (VIE) solver of Sayed, Liu, Gomez and Yucel,
+ * "A Butterfly-Accelerated Volume Integral Equation Solver for Broad Permittivity
+ * and Large-Scale Electromagnetic Analysis" (IEEE TAP).
+ *
+ * Problem (Section II, eqs. (1)-(2), (4)-(5), scalar Helmholtz kernel, one unknown
+ * per cubic voxel, collocation at voxel centres):
+ *     Z(m,n) = delta_mn / eps_m - K(d_mn) kappa_n,   kappa = (eps - 1) / eps,
+ *     K(d)   = (k h)^2 / (4 pi |d|) exp(-j k h |d|)   for integer voxel offsets d != 0,
+ *     K(0)   = (1 + j k a) exp(-j k a) - 1,           a = h (3 / (4 pi))^(1/3),
+ * i.e. k^2 times the Green's function exp(-jkR)/(4 pi R) integrated over the voxel
+ * (one-point rule off the diagonal, the equal-volume sphere on it).  Z I = V is
+ * solved as the right-preconditioned system of eq. (precon).
+ *
+ * Conventions shared by every call:
+ *  - Return value: HODBF_OK (0) or a negative hodbf_status.  No C++ exception
+ *    crosses this ABI.  hodbf_last_error() gives a message for the calling thread.
+ *  - Vectors: complex numbers stored interleaved (re, im).  A block of nrhs vectors
+ *    is column-major in the user's voxel order, element (i, q) at ptr[i + q*ld]
+ *    (in complex elements), user index i = ix + nx*(iy + ny*iz), ld >= N.
+ *    Vector arguments are DEVICE pointers owned by the caller.
+ *  - stream: a hipStream_t (NULL = the null stream).  Calls are stream-ordered
+ *    and return once the work is enqueued, except where stated.
+ *  - Units: free-space wavelength 1 (k0 = 2 pi).  Lossy media have Im(eps) < 0
+ *    (time factor exp(+j w t), matching the exp(-j k R) kernel).
+ *  - An operator is immutable after hodbf_build: const calls on one operator may
+ *    run concurrently on different streams; hodbf_free must not race with them.
+ */
+#ifndef HODBF_H
+#define HODBF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hodbf_op hodbf_op; /* opaque compressed operator (+ preconditioner) */
+
+typedef enum {
+  HODBF_OK = 0,
+  HODBF_E_ARG = -1,     /* invalid argument: shape, pointer, tolerance, eps */
+  HODBF_E_NOMEM = -2,   /* device allocation failed or the HBM budget is exceeded */
+  HODBF_E_HIP = -3,     /* a HIP / rocBLAS / rocSOLVER call failed */
+  HODBF_E_NUMERIC = -4, /* NaN or Inf met in a residual or a factorization */
+  HODBF_E_NOCONV = -5,  /* vie_solve hit max_iter; x holds the last iterate */
+  HODBF_E_STATE = -6    /* the operator lacks what the call needs (no preconditioner) */
+} hodbf_status;
+
+typedef enum { HODBF_C64 = 0, HODBF_C128 = 1 } hodbf_dtype; /* complex FP32 / FP64 */
+
+/* Storage precision of the preconditioner's factors (applies accumulate in FP32). */
+typedef enum {
+  HODBF_P_NONE = 0, /* no preconditioner */
+  HODBF_P_FP32 = 1,
+  HODBF_P_BF16 = 2,
+  HODBF_P_BOTH = 3  /* keep FP32 and BF16 copies (select per solve) */
+} hodbf_prec;
+
+/*
+ * Build parameters.  The voxel grid, per-voxel permittivity and wavenumber state
+ * the scattering problem (Section II); tol_con and tol_fact are the compression
+ * and factorization tolerances chi_con and chi_fact of eq. (precon).
+ */
+typedef struct {
+  int32_t nx, ny, nz;    /* voxel grid, N = nx*ny*nz >= 1 */
+  double h;              /* voxel edge in wavelengths, > 0 */
+  double k0;             /* wavenumber (2 pi for unit wavelength), > 0 */
+  const double *eps_r;   /* HOST, 2N doubles (re, im), user order; copied; eps != 0 */
+  double tol_con;        /* chi_con in (0, 1): ID truncation of the forward operator */
+  double tol_fact;       /* chi_fact in (0, 1): ID truncation of the inverse factors */
+  int32_t leaf_size;     /* leaf cluster size of T_H, 1..64 (64 recommended) */
+  int32_t precond_prec;  /* hodbf_prec */
+  int32_t precond_min_level; /* levels < this get no X_tau (0 = full Algorithm 1 form) */
+  uint64_t seed;         /* row-sampling RNG seed */
+  size_t hbm_budget;     /* bytes of device memory the operator may hold; 0 = unlimited */
+  void *stream;          /* hipStream_t used for construction */
+} hodbf_build_params;
+
+/*
+ * hodbf_build -- compress Z in HOD-BF form (Section III-A: cluster tree T_H, dense
+ * leaf blocks D_tau, nested-ID butterflies for every off-diagonal sibling block) and,
+ * if precond_prec != HODBF_P_NONE, its approximate inverse in the multiplicative
+ * form of Algorithm 1 (Section III-B).  Blocks until the operator is ready.
+ * *out receives a new operator owned by the caller (release with hodbf_free).
+ * Errors: E_ARG (bad grid, h, k0, tolerance, leaf size, eps = 0 or non-finite),
+ * E_NOMEM (allocation or hbm_budget), E_HIP, E_NUMERIC (singular diagonal block).
+ */
+hodbf_status hodbf_build(const hodbf_build_params *params, hodbf_op **out);
+
+/*
+ * hodbf_apply -- y = Z_con x for nrhs >= 0 vectors (Section III-A, the butterfly
+ * product B^L W^L ... W^1 V^0 of eq. (butterfly_mat) for every off-diagonal block
+ * plus the dense leaf blocks).  Arithmetic is complex FP32 with FP32 accumulation
+ * whatever dtype is; dtype only sets the storage type of x and y.
+ * x and y must not overlap.  nrhs == 0 is a no-op.
+ */
+hodbf_status hodbf_apply(const hodbf_op *op, int32_t nrhs, hodbf_dtype dtype,
+                         const void *x, int64_t ldx, void *y, int64_t ldy, void *stream);
+
+/*
+ * hodbf_precond_apply -- y = P x with P ~ Z^{-1}: the leaf inverses D_tau^{-1}
+ * followed, level by level towards the root, by z(tau) <- (I + X_tau) z(tau)
+ * (Algorithm 1 unrolled).  Factors in the operator's stored precision (BF16 if
+ * present, else FP32), FP32 accumulation.  E_STATE if built without one.
+ */
+hodbf_status hodbf_precond_apply(const hodbf_op *op, int32_t nrhs, hodbf_dtype dtype,
+                                 const void *x, int64_t ldx, void *y, int64_t ldy,
+                                 void *stream);
+
+typedef struct {
+  double tol;           /* chi_sol: stop when ||b - Z x|| / ||b|| <= tol per column */
+  int32_t restart;      /* GMRES restart length m, 1..200 (20 recommended) */
+  int32_t max_iter;     /* cap on Arnoldi steps per column (the paper caps at 3000) */
+  int32_t use_precond;  /* 0: none; 1: operator default; HODBF_P_FP32 / HODBF_P_BF16 + 8 */
+} hodbf_solve_opts;
+
+typedef struct {
+  int32_t *iters;       /* HOST, nrhs: Arnoldi steps (products with Z) per column */
+  int32_t *converged;   /* HOST, nrhs: 1 if the true residual met tol */
+  double *relres;       /* HOST, nrhs: final true relative residual ||b - Z x|| / ||b|| */
+} hodbf_solve_info;
+
+/*
+ * vie_solve -- solve Z x = b (eq. (4)) for nrhs columns with right-preconditioned
+ * flexible GMRES(m), all Krylov arithmetic in complex FP64 on the device
+ * (classical Gram-Schmidt applied twice, Givens rotations, true residual check),
+ * products with Z and P as in hodbf_apply / hodbf_precond_apply.  b and x are
+ * complex FP64 DEVICE arrays (user order, ld >= N); x is overwritten (x0 = 0).
+ * Blocks until done (reads one small convergence flag per Arnoldi step).
+ * info may be NULL.  E_NOCONV if any column missed tol within max_iter.
+ */
+hodbf_status vie_solve(const hodbf_op *op, int32_t nrhs, const void *b, int64_t ldb,
+                       void *x, int64_t ldx, const hodbf_solve_opts *opts,
+                       hodbf_solve_info *info, void *stream);
+
+/*
+ * hodbf_plane_wave -- b(:, q) = exp(-j k0 dhat_q . (r - r_c)) at the voxel centres
+ * r = h (i + 1/2), r_c the box centre (the plane-wave excitation of Section IV).
+ * dirs: HOST, 3*nrhs doubles (unit vectors).  b: complex FP64 DEVICE, ld >= N.
+ */
+hodbf_status hodbf_plane_wave(const hodbf_op *op, int32_t nrhs, const double *dirs,
+                              void *b, int64_t ldb, void *stream);
+
+typedef struct {
+  int64_t n;                 /* unknowns */
+  int32_t levels;            /* L_H */
+  int32_t leaves;            /* 2^L_H */
+  int32_t max_rank;          /* largest butterfly rank of the forward operator */
+  int32_t precond_max_rank;  /* largest butterfly rank of the X_tau factors */
+  int64_t entries_fwd;       /* stored complex entries of Z_con (dense leaves + factors) */
+  int64_t entries_pre;       /* stored complex entries of the preconditioner */
+  int64_t bytes_fwd;         /* device bytes of the forward factors */
+  int64_t bytes_pre;         /* device bytes of the preconditioner factors (all copies) */
+  int64_t bytes_total;       /* device bytes held by the operator */
+  int32_t fwd_stages;        /* grouped launches per forward apply */
+  int32_t pre_stages;        /* grouped launches per preconditioner apply */
+  double build_seconds;      /* wall time of the forward construction */
+  double precond_seconds;    /* wall time of the preconditioner construction */
+  int64_t id_count;          /* interpolative decompositions computed */
+} hodbf_stats_t;
+
+hodbf_status hodbf_stats(const hodbf_op *op, hodbf_stats_t *st);
+
+/*
+ * hodbf_export -- copy operator internals to HOST memory for verification.
+ * which: 0 perm (int32 N: tree position -> user index);
+ *        1 forward block table, 2 forward factor values (complex FP32),
+ *        3 preconditioner block table, 4 preconditioner values (complex FP32,
+ *          converted from the stored precision, FP32 copy if both are stored),
+ *        5 preconditioner values of the BF16 copy (converted to complex FP32).
+ * Block tables are int64 rows of 11: kind (0 dense leaf, 1 V0, 2 W, 3 B),
+ * hod level l, node i, child row ca, child col cb, butterfly level, a, b, rows m,
+ * cols n, offset (complex elements into the values, column-major m x n).
+ * Call with buf == NULL to get the size in *bytes; E_ARG if *bytes is too small.
+ */
+hodbf_status hodbf_export(const hodbf_op *op, int32_t which, void *buf, size_t *bytes);
+
+void hodbf_free(hodbf_op *op);
+const char *hodbf_last_error(void);
+
+/*
+ * hodbf_plan_probe -- run only the host part of the forward construction (cluster
+ * tree, row sampling, interpolative decompositions) and export it, without touching
+ * a GPU.  which: 0 perm (int32 N); 1 block table (as above, kind 3 rows give the
+ * skeleton count in n and an offset into the skeleton list); 2 V0/W values
+ * (complex FP64); 6 B-block skeleton columns (int32 tree positions).
+ * For host-logic verification.  Same size protocol as hodbf_export.
+ */
+hodbf_status hodbf_plan_probe(const hodbf_build_params *params, int32_t which, void *buf,
+                              size_t *bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HODBF_H */

@@ -1,0 +1,89 @@
+// Descriptors and launch wrappers shared by host code and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace hodbf {
+
+// One output segment of a grouped complex GEMM: rows [out_row, out_row + m) of the
+// output buffer (m <= 64) receive the sum over pairs [p0, p1) of A_p * in_p.
+struct Seg {
+  int32_t out_row, m, p0, p1;
+};
+
+// A factor block (column-major, element (i, k) at f_off + k * lda + i) times the
+// input rows [in_row, in_row + n) of buffer X (in_buf = 0) or T (in_buf = 1).
+struct Pair {
+  int64_t f_off;
+  int32_t in_row, n, lda, in_buf;
+};
+
+// Device entry-generation job: column-major block of Z, rows r0..r0+m (tree order,
+// contiguous), columns cols[c_off .. c_off + n) (tree positions).
+struct EntryJob {
+  int64_t f_off;
+  int32_t r0, m, c_off, n;
+};
+
+enum FactorType { FT_C64 = 0, FT_BF16 = 1 };
+
+// Grouped GEMM over segs[s0, s0 + ns): OUT(seg rows) = beta * OUT + sum A * in.
+// X, T, OUT: complex FP32 RHS-interleaved (element (row, q) at row * R + q).
+void launch_grouped(const Seg *segs, const Pair *pairs, int64_t s0, int64_t ns, const void *F,
+                    int ftype, const float2 *X, const float2 *T, float2 *OUT, int R, int beta,
+                    hipStream_t st);
+
+void launch_entries(const EntryJob *jobs, int64_t njobs, const int32_t *cols, const short4 *xyz,
+                    const double2 *inv_eps, const double2 *kappa, double kh, double2 k2S,
+                    float2 *F32, double2 *F64, hipStream_t st);
+
+// user-order column-major (ld) <-> tree-order RHS-interleaved, with dtype conversion.
+// src_c128 / dst_c128 select complex FP64 (true) or FP32 (false) on the user side;
+// the tree side is complex FP32 (tree_c128 = false) or FP64.
+void launch_gather(const void *src, bool src_c128, int64_t ld, void *dst, bool dst_c128,
+                   const int32_t *perm, int64_t n, int R, hipStream_t st);
+void launch_scatter(const void *src, bool src_c128, void *dst, bool dst_c128, int64_t ld,
+                    const int32_t *perm, int64_t n, int R, hipStream_t st);
+
+void launch_plane_wave(const double *dirs_dev, int R, int nx, int ny, int nz, double h,
+                       double k0, double2 *b, int64_t ldb, hipStream_t st);
+
+// ---- FP64 Krylov kernels (tree order, RHS-interleaved, complex FP64) ----
+void launch_c128_to_c64(const double2 *src, float2 *dst, int64_t count, hipStream_t st);
+void launch_c64_to_c128(const float2 *src, double2 *dst, int64_t count, hipStream_t st);
+// partial[b][i][q] = sum over rows of block b of conj(V_i(row, q)) * w(row, q), i < nv
+void launch_multidot(const double2 *V, int64_t vstride, int nv, const double2 *w, int64_t n,
+                     int R, double2 *partial, int nblk, hipStream_t st);
+// out[i][q] (+)= sum_b partial[b][i][q]
+void launch_reduce_partials(const double2 *partial, int nblk, int nv, int R, double2 *out,
+                            int accumulate, hipStream_t st);
+int multidot_blocks(int64_t n, int R);
+// w -= sum_i V_i * h[i][q]
+void launch_vupdate(const double2 *V, int64_t vstride, int nv, const double2 *h, double2 *w,
+                    int64_t n, int R, hipStream_t st);
+// v = w / hnorm[q] (0 where hnorm is tiny), hnorm given as |.|^2 in re of sq[q]
+void launch_normalize(const double2 *w, const double2 *sq, double2 *v, double2 *hcol,
+                      int64_t n, int R, const int32_t *active, hipStream_t st);
+// x += sum_i Zs_i y_i (Zs complex FP32)
+void launch_xupdate(const float2 *Zs, int64_t zstride, int nv, const double2 *y, double2 *x,
+                    int64_t n, int R, hipStream_t st);
+// out = a - b
+void launch_axpby(const double2 *a, const double2 *b, double2 *out, int64_t count, hipStream_t st);
+
+// Per-column GMRES bookkeeping on the device.  H is stored column by column: column j
+// at H + j * (m + 1) * R, entry (i, q) at i * R + q.
+struct GmresState {
+  double2 *H, *cs, *sn, *g, *y;
+  double *bnorm, *est;
+  int32_t *jend;    // steps kept in this cycle; -1 while still iterating
+  int32_t *active;  // 0 once a column has converged (true residual)
+  int m, R;
+};
+void launch_givens(GmresState s, int j, double tol, hipStream_t st);
+void launch_lsq(GmresState s, hipStream_t st);
+void launch_cycle_init(GmresState s, const double2 *sq, hipStream_t st);
+void launch_mask_cols(double2 *v, const int32_t *active, int64_t n, int R, hipStream_t st);
+
+}  // namespace hodbf

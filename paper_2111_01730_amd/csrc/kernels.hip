@@ -1,0 +1,465 @@
+// HIP kernels for gfx950: entry generation, permutation, and the grouped complex GEMM
+// that applies every butterfly factor stage and the leaf / outer blocks.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "device.h"
+
+namespace hodbf {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef short shortx4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// Entry generation (K1).  Z(m, n) = delta_mn / eps_m - K(d_mn) kappa_n with
+// K(d) = (kh)^2 / (4 pi |d|) exp(-j kh |d|), K(0) = k^2 S(a) (Section II, voxel
+// collocation).  Distances come from exact integer offsets; the phase is evaluated
+// in FP64 so that large k|R| keeps full accuracy, then rounded to the output type.
+__global__ __launch_bounds__(256) void k_entries(const EntryJob *__restrict__ jobs,
+                                                 const int32_t *__restrict__ cols,
+                                                 const short4 *__restrict__ xyz,
+                                                 const double2 *__restrict__ inv_eps,
+                                                 const double2 *__restrict__ kappa, double kh,
+                                                 double2 k2S, float2 *__restrict__ F32,
+                                                 double2 *__restrict__ F64) {
+  const EntryJob jb = jobs[blockIdx.x];
+  const int64_t total = int64_t(jb.m) * jb.n;
+  const double c0 = kh * kh * (1.0 / (4.0 * M_PI));
+  for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
+    const int i = int(e % jb.m);
+    const int k = int(e / jb.m);
+    const int32_t row = jb.r0 + i;
+    const int32_t col = cols[jb.c_off + k];
+    const short4 a = xyz[row], b = xyz[col];
+    const int dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
+    const int d2 = dx * dx + dy * dy + dz * dz;
+    const double2 kap = kappa[col];
+    double2 z;
+    if (d2 == 0) {
+      const double2 ie = inv_eps[row];
+      z.x = ie.x - (k2S.x * kap.x - k2S.y * kap.y);
+      z.y = ie.y - (k2S.x * kap.y + k2S.y * kap.x);
+    } else {
+      const double rho = sqrt(double(d2));
+      const double s = c0 / rho;
+      double sn, cs;
+      sincos(kh * rho, &sn, &cs);
+      const double kr = s * cs, ki = -s * sn;  // K(d)
+      z.x = -(kr * kap.x - ki * kap.y);
+      z.y = -(kr * kap.y + ki * kap.x);
+    }
+    if (F32) F32[jb.f_off + e] = make_float2(float(z.x), float(z.y));
+    if (F64) F64[jb.f_off + e] = z;
+  }
+}
+
+void launch_entries(const EntryJob *jobs, int64_t njobs, const int32_t *cols, const short4 *xyz,
+                    const double2 *inv_eps, const double2 *kappa, double kh, double2 k2S,
+                    float2 *F32, double2 *F64, hipStream_t st) {
+  for (int64_t j0 = 0; j0 < njobs; j0 += 1 << 30) {
+    const int64_t nj = njobs - j0 < (1 << 30) ? njobs - j0 : (1 << 30);
+    hipLaunchKernelGGL(k_entries, dim3(unsigned(nj)), dim3(256), 0, st, jobs + j0, cols, xyz,
+                       inv_eps, kappa, kh, k2S, F32, F64);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Factor element loads: complex FP32, or complex BF16 packed as (re | im << 16).
+__device__ inline float2 load_factor(const float2 *F, int64_t idx) { return F[idx]; }
+__device__ inline float bf16_to_f(uint32_t h) { return __uint_as_float(h << 16); }
+__device__ inline float2 load_factor(const uint32_t *F, int64_t idx) {
+  const uint32_t w = F[idx];
+  return make_float2(bf16_to_f(w & 0xFFFFu), bf16_to_f(w >> 16));
+}
+
+// Small-R grouped GEMM: one wave per segment.  Lanes split the m <= 64 rows and a few
+// k-groups; factor columns are read coalesced, input values broadcast.
+template <typename FT>
+__global__ __launch_bounds__(256) void k_grouped_gemv(const Seg *__restrict__ segs,
+                                                      const Pair *__restrict__ pairs,
+                                                      const FT *__restrict__ F,
+                                                      const float2 *__restrict__ X,
+                                                      const float2 *__restrict__ T,
+                                                      float2 *__restrict__ OUT, int R,
+                                                      int beta, int64_t nseg) {
+  const int64_t w = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  if (w >= nseg) return;
+  const int lane = threadIdx.x & 63;
+  const Seg sg = segs[w];
+  const int m = sg.m;
+  const int mp = m <= 16 ? 16 : (m <= 32 ? 32 : 64);
+  const int G = 64 / mp;
+  const int i = lane % mp, g = lane / mp;
+  for (int q0 = 0; q0 < R; q0 += 4) {
+    const int nq = R - q0 < 4 ? R - q0 : 4;
+    float ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
+    for (int p = sg.p0; p < sg.p1; ++p) {
+      const Pair pr = pairs[p];
+      const float2 *in = (pr.in_buf ? T : X) + int64_t(pr.in_row) * R + q0;
+      for (int k = g; k < pr.n; k += G) {
+        const float2 a = i < m ? load_factor(F, pr.f_off + int64_t(k) * pr.lda + i)
+                               : make_float2(0.f, 0.f);
+        const float2 *xk = in + int64_t(k) * R;
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) {
+          if (qq < nq) {
+            const float2 x = xk[qq];
+            ar[qq] += a.x * x.x - a.y * x.y;
+            ai[qq] += a.x * x.y + a.y * x.x;
+          }
+        }
+      }
+    }
+    for (int off = mp; off < 64; off <<= 1) {
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) {
+        ar[qq] += __shfl_xor(ar[qq], off);
+        ai[qq] += __shfl_xor(ai[qq], off);
+      }
+    }
+    if (g == 0 && i < m) {
+      float2 *o = OUT + int64_t(sg.out_row + i) * R + q0;
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) {
+        if (qq < nq) {
+          float2 v = make_float2(ar[qq], ai[qq]);
+          if (beta) {
+            const float2 u = o[qq];
+            v.x += u.x;
+            v.y += u.y;
+          }
+          o[qq] = v;
+        }
+      }
+    }
+  }
+}
+
+// MFMA grouped GEMM, complex FP32 factors.  The complex product is one real GEMM:
+// a factor row (ar_0, ai_0, ar_1, ai_1, ...) times Xt, where Xt row 2c holds
+// (xr, xi) and row 2c+1 holds (-xi, xr) for every right-hand side, so output column
+// pair (2q, 2q+1) is (Re y_q, Im y_q).  v_mfma_f32_16x16x4f32: lane l holds
+// A[l % 16][l / 16], B[l / 16][l % 16], and D[4 (l / 16) + v][l % 16].  Four
+// MFMAs consume 8 complex columns: slot kk of MFMA t is real column 4 kk + t, i.e.
+// complex column 2 kk + t / 2, part t % 2.  Each workgroup owns one segment (<= 64
+// rows = 4 row tiles); its waves split row tiles and 8-RHS column tiles.
+__global__ __launch_bounds__(256) void k_grouped_mfma_f32(const Seg *__restrict__ segs,
+                                                          const Pair *__restrict__ pairs,
+                                                          const float2 *__restrict__ F,
+                                                          const float2 *__restrict__ X,
+                                                          const float2 *__restrict__ T,
+                                                          float2 *__restrict__ OUT, int R,
+                                                          int beta) {
+  const Seg sg = segs[blockIdx.x];
+  const int m = sg.m;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nrt = (m + 15) >> 4;
+  const int nrtp = nrt == 3 ? 4 : nrt;
+  const int wpr = 4 / nrtp;
+  const int rt = wave / wpr;
+  if (rt >= nrt) return;
+  const int sub = wave % wpr;
+  const int ia = rt * 16 + (lane & 15);  // A row of this lane
+  const int kk = lane >> 4;
+  const int jc = lane & 15;
+  const int qo = jc >> 1, op = jc & 1;
+  for (int q0 = 0; q0 < R; q0 += 64) {
+    const int Rc = R - q0 < 64 ? R - q0 : 64;
+    const int nnt = (Rc + 7) >> 3;
+    floatx4 acc[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int p = sg.p0; p < sg.p1; ++p) {
+      const Pair pr = pairs[p];
+      const float2 *A = F + pr.f_off;
+      const float2 *in = (pr.in_buf ? T : X) + int64_t(pr.in_row) * R;
+      const int n = pr.n;
+      for (int c0 = 0; c0 < n; c0 += 8) {
+        const int c = c0 + 2 * kk;
+        const bool rok = ia < m;
+        const float2 z2 = make_float2(0.f, 0.f);
+        const float2 a0 = (rok && c < n) ? A[int64_t(c) * pr.lda + ia] : z2;
+        const float2 a1 = (rok && c + 1 < n) ? A[int64_t(c + 1) * pr.lda + ia] : z2;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int nt = sub + j * wpr;
+          if (nt < nnt) {
+            const int q = q0 + nt * 8 + qo;
+            const bool qok = q < R;
+            const float2 x0 = (qok && c < n) ? in[int64_t(c) * R + q] : z2;
+            const float2 x1 = (qok && c + 1 < n) ? in[int64_t(c + 1) * R + q] : z2;
+            const float b0 = op ? x0.y : x0.x;
+            const float b1 = op ? x0.x : -x0.y;
+            const float b2 = op ? x1.y : x1.x;
+            const float b3 = op ? x1.x : -x1.y;
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.x, b0, acc[j], 0, 0, 0);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.y, b1, acc[j], 0, 0, 0);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.x, b2, acc[j], 0, 0, 0);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.y, b3, acc[j], 0, 0, 0);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int nt = sub + j * wpr;
+      if (nt < nnt) {
+        const int q = q0 + nt * 8 + qo;
+        if (q < R) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = rt * 16 + 4 * kk + v;
+            if (row < m) {
+              float *o = reinterpret_cast<float *>(OUT + int64_t(sg.out_row + row) * R + q) + op;
+              *o = beta ? *o + acc[j][v] : acc[j][v];
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+// MFMA grouped GEMM, complex BF16 factors (v_mfma_f32_16x16x16bf16_1k): one MFMA
+// consumes 8 complex columns; lane slot kk holds real columns 4 kk .. 4 kk + 3, i.e.
+// (Re, Im) of complex columns 2 kk and 2 kk + 1.  Inputs are rounded to BF16 with
+// round-to-nearest-even; accumulation is FP32.
+__device__ inline short f_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return short(u >> 16);
+}
+
+__global__ __launch_bounds__(256) void k_grouped_mfma_bf16(const Seg *__restrict__ segs,
+                                                           const Pair *__restrict__ pairs,
+                                                           const uint32_t *__restrict__ F,
+                                                           const float2 *__restrict__ X,
+                                                           const float2 *__restrict__ T,
+                                                           float2 *__restrict__ OUT, int R,
+                                                           int beta) {
+  const Seg sg = segs[blockIdx.x];
+  const int m = sg.m;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nrt = (m + 15) >> 4;
+  const int nrtp = nrt == 3 ? 4 : nrt;
+  const int wpr = 4 / nrtp;
+  const int rt = wave / wpr;
+  if (rt >= nrt) return;
+  const int sub = wave % wpr;
+  const int ia = rt * 16 + (lane & 15);
+  const int kk = lane >> 4;
+  const int jc = lane & 15;
+  const int qo = jc >> 1, op = jc & 1;
+  for (int q0 = 0; q0 < R; q0 += 64) {
+    const int Rc = R - q0 < 64 ? R - q0 : 64;
+    const int nnt = (Rc + 7) >> 3;
+    floatx4 acc[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int p = sg.p0; p < sg.p1; ++p) {
+      const Pair pr = pairs[p];
+      const uint32_t *A = F + pr.f_off;
+      const float2 *in = (pr.in_buf ? T : X) + int64_t(pr.in_row) * R;
+      const int n = pr.n;
+      for (int c0 = 0; c0 < n; c0 += 8) {
+        const int c = c0 + 2 * kk;
+        const bool rok = ia < m;
+        const uint32_t w0 = (rok && c < n) ? A[int64_t(c) * pr.lda + ia] : 0u;
+        const uint32_t w1 = (rok && c + 1 < n) ? A[int64_t(c + 1) * pr.lda + ia] : 0u;
+        shortx4 av;
+        av[0] = short(w0 & 0xFFFFu);
+        av[1] = short(w0 >> 16);
+        av[2] = short(w1 & 0xFFFFu);
+        av[3] = short(w1 >> 16);
+        const float2 z2 = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int nt = sub + j * wpr;
+          if (nt < nnt) {
+            const int q = q0 + nt * 8 + qo;
+            const bool qok = q < R;
+            const float2 x0 = (qok && c < n) ? in[int64_t(c) * R + q] : z2;
+            const float2 x1 = (qok && c + 1 < n) ? in[int64_t(c + 1) * R + q] : z2;
+            shortx4 bv;
+            bv[0] = f_to_bf16(op ? x0.y : x0.x);
+            bv[1] = f_to_bf16(op ? x0.x : -x0.y);
+            bv[2] = f_to_bf16(op ? x1.y : x1.x);
+            bv[3] = f_to_bf16(op ? x1.x : -x1.y);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[j], 0, 0, 0);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int nt = sub + j * wpr;
+      if (nt < nnt) {
+        const int q = q0 + nt * 8 + qo;
+        if (q < R) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = rt * 16 + 4 * kk + v;
+            if (row < m) {
+              float *o = reinterpret_cast<float *>(OUT + int64_t(sg.out_row + row) * R + q) + op;
+              *o = beta ? *o + acc[j][v] : acc[j][v];
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+void launch_grouped(const Seg *segs, const Pair *pairs, int64_t s0, int64_t ns, const void *F,
+                    int ftype, const float2 *X, const float2 *T, float2 *OUT, int R, int beta,
+                    hipStream_t st) {
+  if (ns <= 0 || R <= 0) return;
+  const Seg *sp = segs + s0;
+  if (R < 4) {
+    const int64_t nb = (ns + 3) / 4;
+    if (ftype == FT_C64)
+      hipLaunchKernelGGL(k_grouped_gemv<float2>, dim3(unsigned(nb)), dim3(256), 0, st, sp, pairs,
+                         static_cast<const float2 *>(F), X, T, OUT, R, beta, ns);
+    else
+      hipLaunchKernelGGL(k_grouped_gemv<uint32_t>, dim3(unsigned(nb)), dim3(256), 0, st, sp,
+                         pairs, static_cast<const uint32_t *>(F), X, T, OUT, R, beta, ns);
+    return;
+  }
+  if (ftype == FT_C64)
+    hipLaunchKernelGGL(k_grouped_mfma_f32, dim3(unsigned(ns)), dim3(256), 0, st, sp, pairs,
+                       static_cast<const float2 *>(F), X, T, OUT, R, beta);
+  else
+    hipLaunchKernelGGL(k_grouped_mfma_bf16, dim3(unsigned(ns)), dim3(256), 0, st, sp, pairs,
+                       static_cast<const uint32_t *>(F), X, T, OUT, R, beta);
+}
+
+// ---------------------------------------------------------------------------
+// Permutation between the user's column-major order and the internal tree-order,
+// RHS-interleaved layout, staged through LDS so both sides are read / written in runs.
+template <typename S, typename D>
+__device__ inline D cvt(S v);
+template <>
+__device__ inline float2 cvt<float2, float2>(float2 v) { return v; }
+template <>
+__device__ inline double2 cvt<double2, double2>(double2 v) { return v; }
+template <>
+__device__ inline float2 cvt<double2, float2>(double2 v) {
+  return make_float2(float(v.x), float(v.y));
+}
+template <>
+__device__ inline double2 cvt<float2, double2>(float2 v) {
+  return make_double2(double(v.x), double(v.y));
+}
+
+template <typename S, typename D>
+__global__ __launch_bounds__(256) void k_gather(const S *__restrict__ src, int64_t ld,
+                                                D *__restrict__ dst,
+                                                const int32_t *__restrict__ perm, int64_t n,
+                                                int R) {
+  __shared__ D tile[64][33];
+  const int64_t i0 = int64_t(blockIdx.x) * 64;
+  const int q0 = blockIdx.y * 32;
+  for (int e = threadIdx.x; e < 64 * 32; e += 256) {
+    const int il = e & 63, ql = e >> 6;
+    const int64_t i = i0 + il;
+    const int q = q0 + ql;
+    if (i < n && q < R) tile[il][ql] = cvt<S, D>(src[int64_t(perm[i]) + int64_t(q) * ld]);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 64 * 32; e += 256) {
+    const int ql = e & 31, il = e >> 5;
+    const int64_t i = i0 + il;
+    const int q = q0 + ql;
+    if (i < n && q < R) dst[i * R + q] = tile[il][ql];
+  }
+}
+
+template <typename S, typename D>
+__global__ __launch_bounds__(256) void k_scatter(const S *__restrict__ src, D *__restrict__ dst,
+                                                 int64_t ld, const int32_t *__restrict__ perm,
+                                                 int64_t n, int R) {
+  __shared__ D tile[64][33];
+  const int64_t i0 = int64_t(blockIdx.x) * 64;
+  const int q0 = blockIdx.y * 32;
+  for (int e = threadIdx.x; e < 64 * 32; e += 256) {
+    const int ql = e & 31, il = e >> 5;
+    const int64_t i = i0 + il;
+    const int q = q0 + ql;
+    if (i < n && q < R) tile[il][ql] = cvt<S, D>(src[i * R + q]);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 64 * 32; e += 256) {
+    const int il = e & 63, ql = e >> 6;
+    const int64_t i = i0 + il;
+    const int q = q0 + ql;
+    if (i < n && q < R) dst[int64_t(perm[i]) + int64_t(q) * ld] = tile[il][ql];
+  }
+}
+
+void launch_gather(const void *src, bool src_c128, int64_t ld, void *dst, bool dst_c128,
+                   const int32_t *perm, int64_t n, int R, hipStream_t st) {
+  if (n <= 0 || R <= 0) return;
+  dim3 grid(unsigned((n + 63) / 64), unsigned((R + 31) / 32));
+  if (src_c128 && dst_c128)
+    hipLaunchKernelGGL((k_gather<double2, double2>), grid, dim3(256), 0, st,
+                       (const double2 *)src, ld, (double2 *)dst, perm, n, R);
+  else if (src_c128)
+    hipLaunchKernelGGL((k_gather<double2, float2>), grid, dim3(256), 0, st,
+                       (const double2 *)src, ld, (float2 *)dst, perm, n, R);
+  else if (dst_c128)
+    hipLaunchKernelGGL((k_gather<float2, double2>), grid, dim3(256), 0, st,
+                       (const float2 *)src, ld, (double2 *)dst, perm, n, R);
+  else
+    hipLaunchKernelGGL((k_gather<float2, float2>), grid, dim3(256), 0, st, (const float2 *)src,
+                       ld, (float2 *)dst, perm, n, R);
+}
+
+void launch_scatter(const void *src, bool src_c128, void *dst, bool dst_c128, int64_t ld,
+                    const int32_t *perm, int64_t n, int R, hipStream_t st) {
+  if (n <= 0 || R <= 0) return;
+  dim3 grid(unsigned((n + 63) / 64), unsigned((R + 31) / 32));
+  if (src_c128 && dst_c128)
+    hipLaunchKernelGGL((k_scatter<double2, double2>), grid, dim3(256), 0, st,
+                       (const double2 *)src, (double2 *)dst, ld, perm, n, R);
+  else if (src_c128)
+    hipLaunchKernelGGL((k_scatter<double2, float2>), grid, dim3(256), 0, st,
+                       (const double2 *)src, (float2 *)dst, ld, perm, n, R);
+  else if (dst_c128)
+    hipLaunchKernelGGL((k_scatter<float2, double2>), grid, dim3(256), 0, st,
+                       (const float2 *)src, (double2 *)dst, ld, perm, n, R);
+  else
+    hipLaunchKernelGGL((k_scatter<float2, float2>), grid, dim3(256), 0, st, (const float2 *)src,
+                       (float2 *)dst, ld, perm, n, R);
+}
+
+// ---------------------------------------------------------------------------
+// Plane-wave excitation (Section IV): b(i, q) = exp(-j k0 dhat_q . (r_i - r_c)).
+__global__ __launch_bounds__(256) void k_plane_wave(const double *__restrict__ dirs, int R,
+                                                    int nx, int ny, int nz, double h, double k0,
+                                                    double2 *__restrict__ b, int64_t ldb) {
+  const int64_t n = int64_t(nx) * ny * nz;
+  const int q = blockIdx.y;
+  const double dx = dirs[3 * q], dy = dirs[3 * q + 1], dz = dirs[3 * q + 2];
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int ix = int(i % nx), iy = int((i / nx) % ny), iz = int(i / (int64_t(nx) * ny));
+    const double rx = h * (ix + 0.5 - 0.5 * nx), ry = h * (iy + 0.5 - 0.5 * ny),
+                 rz = h * (iz + 0.5 - 0.5 * nz);
+    double s, c;
+    sincos(-k0 * (dx * rx + dy * ry + dz * rz), &s, &c);
+    b[i + int64_t(q) * ldb] = make_double2(c, s);
+  }
+}
+
+void launch_plane_wave(const double *dirs_dev, int R, int nx, int ny, int nz, double h,
+                       double k0, double2 *b, int64_t ldb, hipStream_t st) {
+  const int64_t n = int64_t(nx) * ny * nz;
+  if (n <= 0 || R <= 0) return;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_plane_wave, dim3(unsigned(blocks), unsigned(R)), dim3(256), 0, st,
+                     dirs_dev, R, nx, ny, nz, h, k0, b, ldb);
+}
+
+}  // namespace hodbf

@@ -1,0 +1,28 @@
+// Accumulator used while packing butterfly factors into a device program.
+#pragma once
+
+#include <functional>
+#include <vector>
+
+#include "op.h"
+
+namespace hodbf {
+
+struct PackSink {
+  std::vector<Seg> segs;
+  std::vector<Pair> pairs;
+  std::vector<Launch> launches;
+  int64_t t_rows = 0;
+  std::vector<BlockRec> *table = nullptr;
+  std::function<int64_t(const Mat &)> put_host;          // host-valued block -> arena offset
+  std::function<int64_t(int64_t, int64_t)> reserve_dev;  // device-generated block -> offset
+  std::vector<EntryJob> *jobs = nullptr;
+  std::vector<int32_t> *jobcols = nullptr;
+};
+
+void pack_group(PackSink &pk, const Tree &t, const std::vector<const Butterfly *> &bfs,
+                bool forward, int final_beta,
+                const std::function<void(const Butterfly &, int64_t *)> &meta);
+void upload_program(Program &prog, PackSink &pk, hipStream_t st);
+
+}  // namespace hodbf

@@ -1,0 +1,134 @@
+"""Python face of the hodbf library: torch tensors for device memory and streams only.
+
+Every method marshals arguments to one C-ABI call of ``libhodbf.so``; no arithmetic of
+the method happens here.  Vectors are torch tensors of shape (N,) or (N, R) on the GPU,
+complex64 or complex128, in the user's voxel order (i = ix + nx*(iy + ny*iz)).
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import C64, C128, P_BF16, P_BOTH, P_FP32, P_NONE, check, lib
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _as_cols(x: torch.Tensor, n: int):
+    """View (N,) or (N, R) as a column-major block: returns (tensor of shape (R, N), R)."""
+    if x.dim() == 1:
+        x = x.unsqueeze(1)
+    if x.shape[0] != n:
+        raise ValueError(f"expected {n} rows, got {tuple(x.shape)}")
+    if not x.is_cuda:
+        raise ValueError("vectors must live on the GPU")
+    if x.dtype not in (torch.complex64, torch.complex128):
+        raise ValueError("vectors must be complex64 or complex128")
+    return x.t().contiguous(), x.shape[1]
+
+
+class Operator:
+    """A compressed VIE system matrix (and optional preconditioner) resident on the GPU."""
+
+    def __init__(self, grid, tol_con=1e-4, tol_fact=0.0, leaf_size=64, precond=P_NONE,
+                 precond_min_level=0, seed=1, hbm_budget=0):
+        self.grid = grid
+        self.n = grid.n
+        p = _lib.make_params(grid, tol_con, tol_fact, leaf_size, precond, precond_min_level,
+                             seed, hbm_budget, _stream())
+        h = C.c_void_p()
+        check(lib().hodbf_build(C.byref(p), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().hodbf_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _call_apply(self, fn, x, out_dtype=None):
+        xc, R = _as_cols(x, self.n)
+        dt = C128 if xc.dtype == torch.complex128 else C64
+        y = torch.empty_like(xc)
+        check(fn(self._h, R, dt, C.c_void_p(xc.data_ptr()), self.n, C.c_void_p(y.data_ptr()),
+                 self.n, _stream()))
+        y = y.t()
+        return y[:, 0] if x.dim() == 1 else y
+
+    def apply(self, x: torch.Tensor) -> torch.Tensor:
+        """y = Z_con x."""
+        return self._call_apply(lib().hodbf_apply, x)
+
+    def precond_apply(self, x: torch.Tensor) -> torch.Tensor:
+        """y = P x with P ~ Z^{-1}."""
+        return self._call_apply(lib().hodbf_precond_apply, x)
+
+    def plane_wave(self, dirs) -> torch.Tensor:
+        d = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64).reshape(-1, 3))
+        R = d.shape[0]
+        b = torch.empty((R, self.n), dtype=torch.complex128, device="cuda")
+        check(lib().hodbf_plane_wave(self._h, R, d.ctypes.data_as(C.POINTER(C.c_double)),
+                                     C.c_void_p(b.data_ptr()), self.n, _stream()))
+        return b.t()
+
+    def solve(self, b: torch.Tensor, tol=1e-4, restart=20, max_iter=3000, use_precond=1):
+        """x ~ Z^{-1} b by right-preconditioned FGMRES; returns (x, info dict).
+
+        use_precond: 0 none, 1 the operator's default copy, 'fp32' or 'bf16'.
+        """
+        if b.dtype != torch.complex128:
+            raise ValueError("b must be complex128")
+        bc, R = _as_cols(b, self.n)
+        x = torch.empty_like(bc)
+        up = {"fp32": 8 + P_FP32, "bf16": 8 + P_BF16}.get(use_precond, use_precond)
+        opts = _lib.SolveOpts(tol=tol, restart=restart, max_iter=max_iter, use_precond=int(up))
+        iters = np.zeros(R, dtype=np.int32)
+        conv = np.zeros(R, dtype=np.int32)
+        rel = np.zeros(R, dtype=np.float64)
+        info = _lib.SolveInfo(iters.ctypes.data_as(C.POINTER(C.c_int32)),
+                              conv.ctypes.data_as(C.POINTER(C.c_int32)),
+                              rel.ctypes.data_as(C.POINTER(C.c_double)))
+        code = lib().vie_solve(self._h, R, C.c_void_p(bc.data_ptr()), self.n,
+                               C.c_void_p(x.data_ptr()), self.n, C.byref(opts), C.byref(info),
+                               _stream())
+        if code not in (_lib.HODBF_OK, -5):
+            check(code)
+        x = x.t()
+        out = dict(iters=iters, converged=conv.astype(bool), relres=rel, status=_lib.STATUS[code])
+        return (x[:, 0] if b.dim() == 1 else x), out
+
+    def stats(self) -> dict:
+        s = _lib.Stats()
+        check(lib().hodbf_stats(self._h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in s._fields_}
+
+    def export(self, which: int, dtype):
+        n = C.c_size_t(0)
+        check(lib().hodbf_export(self._h, which, None, C.byref(n)))
+        out = np.empty(n.value // np.dtype(dtype).itemsize, dtype=dtype)
+        check(lib().hodbf_export(self._h, which, out.ctypes.data_as(C.c_void_p), C.byref(n)))
+        return out
+
+    def perm(self) -> np.ndarray:
+        return self.export(0, np.int32)
+
+    def forward_blocks(self):
+        """(table as int64 (k, 11), values complex64) of the forward operator."""
+        return self.export(1, np.int64).reshape(-1, 11), self.export(2, np.complex64)
+
+    def precond_blocks(self, copy="default"):
+        vals = self.export(5 if copy == "bf16" else 4, np.complex64)
+        return self.export(3, np.int64).reshape(-1, 11), vals
+
+
+__all__ = ["Operator", "P_NONE", "P_FP32", "P_BF16", "P_BOTH"]

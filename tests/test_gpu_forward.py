@@ -1,0 +1,161 @@
+"""GPU parity of the forward HOD-BF apply, entry generation, plane waves and FGMRES
+against the oracle (all through the C ABI)."""
+import numpy as np
+import pytest
+
+from oracle import gmres as ogmres
+from oracle import vie
+from synth import config
+from synth.workloads import make_grid, small_case
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def hod():
+    from paper_2111_01730_amd import hodbf
+    return hodbf
+
+
+def _t(x, dtype=torch.complex128):
+    return torch.as_tensor(np.ascontiguousarray(x)).to(device="cuda", dtype=dtype)
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b, axis=0) / np.linalg.norm(b, axis=0)
+
+
+@pytest.fixture(scope="module")
+def ragged(hod):
+    c = small_case(41, sides=(12, 10, 9), h=0.1, eps_range=(2.0, 10.0), loss=1.0, nrhs=70)
+    g = c["grid"]
+    op = hod.Operator(g, tol_con=1e-4)
+    return c, g, op, vie.dense(g)
+
+
+@pytest.mark.parametrize("R", [1, 2, 3, 4, 8, 13, 64, 70])
+def test_apply_matches_dense_operator(ragged, R):
+    c, g, op, Z = ragged
+    print(f"[apply ragged 12x10x9 R={R}]", flush=True)
+    x = c["x"][:, :R]
+    y = op.apply(_t(x)).cpu().numpy()
+    assert np.all(_rel(y, Z @ x) <= 1e-3)
+
+
+@pytest.mark.parametrize("R", [1, 5, 64])
+def test_apply_arithmetic_parity_with_exported_factors(ragged, R):
+    # the oracle re-applies the GPU's own FP32 factors in FP64: only FP32 rounding differs
+    from tests.plan_tools import hodbf_from_export
+    c, g, op, Z = ragged
+    table, vals = op.forward_blocks()
+    ref = hodbf_from_export(g, op.perm(), table, vals)
+    x = c["x"][:, :R]
+    y = op.apply(_t(x, torch.complex64)).cpu().numpy().astype(np.complex128)
+    xr = x.astype(np.complex64).astype(np.complex128)
+    assert np.all(_rel(y, ref.apply(xr)) <= 2e-5)
+
+
+def test_entry_generation_matches_oracle(ragged):
+    c, g, op, Z = ragged
+    table, vals = op.forward_blocks()
+    perm = op.perm()
+    dense_rows = [r for r in table if r[0] == 0]
+    assert len(dense_rows) == 32
+    lo = 0
+    sizes = []
+    for r in dense_rows:  # leaves are consecutive in tree order
+        m, off = int(r[8]), int(r[10])
+        blk = vals[off:off + m * m].reshape(m, m).T
+        ref = Z[np.ix_(perm[lo:lo + m], perm[lo:lo + m])]
+        assert np.max(np.abs(blk - ref)) <= 2e-7 * np.max(np.abs(ref))
+        lo += m
+        sizes.append(m)
+    assert lo == g.n and set(sizes) <= {33, 34}
+
+
+def test_apply_c1_cube_vs_fft(hod):
+    cfg = config("c1_plain_16")
+    g = cfg["grid"]
+    op = hod.Operator(g, tol_con=cfg["tol"])
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((g.n, 4)) + 1j * rng.standard_normal((g.n, 4))
+    y = op.apply(_t(x)).cpu().numpy()
+    assert np.all(_rel(y, vie.fft_matvec(g, x)) <= 10 * cfg["tol"])
+    st = op.stats()
+    assert st["levels"] == 6 and st["leaves"] == 64 and st["fwd_stages"] == 7
+
+
+def test_apply_c2_full_size_sampled_rows(hod):
+    cfg = config("c2_batched_32")
+    g = cfg["grid"]
+    print("[c2 build]", flush=True)
+    op = hod.Operator(g, tol_con=cfg["tol"])
+    b = op.plane_wave(cfg["dirs"])  # the 64 plane waves of this workload
+    y = op.apply(b).cpu().numpy()
+    bn = b.cpu().numpy()
+    rows = cfg["rows"]
+    ye = vie.direct_rows(g, bn, rows)
+    assert np.all(_rel(y[rows], ye) <= 10 * cfg["tol"])
+    yf = vie.fft_matvec(g, bn[:, :4])
+    assert np.all(_rel(y[:, :4], yf) <= 10 * cfg["tol"])
+
+
+def test_plane_wave_matches_oracle(hod):
+    g = make_grid(7, 6, 5, 0.1, 3.0)
+    op = hod.Operator(g, tol_con=1e-4)
+    d = np.array([[0.0, 0.0, -1.0], [0.6, 0.0, 0.8], [0.36, 0.48, 0.8]])
+    b = op.plane_wave(d).cpu().numpy()
+    assert np.max(np.abs(b - vie.plane_wave(g, d))) <= 1e-13
+
+
+def test_single_leaf_is_dense_and_identity_limit(hod):
+    c = small_case(7, sides=(4, 4, 3), nrhs=5)
+    g = c["grid"]
+    op = hod.Operator(g, tol_con=1e-4)
+    y = op.apply(_t(c["x"])).cpu().numpy()
+    assert np.all(_rel(y, vie.dense(g) @ c["x"]) <= 1e-6)
+    g1 = make_grid(8, 8, 8, 0.125, 1.0)
+    op1 = hod.Operator(g1, tol_con=1e-4)
+    x = np.random.default_rng(1).standard_normal((g1.n, 6)) + 0j
+    assert np.allclose(op1.apply(_t(x)).cpu().numpy(), x, rtol=0, atol=1e-6)
+
+
+def test_zero_rhs_and_errors(hod):
+    from paper_2111_01730_amd._lib import HodbfError
+    g = make_grid(5, 4, 3, 0.1, 2.0)
+    op = hod.Operator(g, tol_con=1e-4)
+    x = torch.zeros((g.n, 0), dtype=torch.complex64, device="cuda")
+    assert op.apply(x).shape == (g.n, 0)
+    with pytest.raises(HodbfError):
+        op.precond_apply(torch.zeros(g.n, dtype=torch.complex64, device="cuda"))
+
+
+def test_gmres_unpreconditioned_matches_lu(hod):
+    c = small_case(51, sides=(8, 8, 6), h=0.1, eps_range=(1.5, 4.0), loss=0.5)
+    g = c["grid"]
+    op = hod.Operator(g, tol_con=1e-6)
+    b = op.plane_wave(c["dirs"])
+    x, info = op.solve(b, tol=1e-6, restart=30, max_iter=600, use_precond=0)
+    assert info["converged"].all(), info
+    Z = vie.dense(g)
+    bn = b.cpu().numpy()
+    xs = ogmres.lu_solve(Z, bn)
+    xn = x.cpu().numpy()
+    assert np.all(_rel(Z @ xn, bn) <= 1e-5)
+    assert np.all(_rel(xn, xs) <= 1e-3)
+    assert np.all(info["relres"] <= 1e-6)
+    # same iteration count as the oracle's FGMRES on the same system, within a few steps
+    _, it, conv, _ = ogmres.fgmres(lambda v: Z @ v, bn[:, 0], None, tol=1e-6, restart=30)
+    assert conv and abs(int(info["iters"][0]) - it) <= 3
+
+
+def test_gmres_zero_rhs_column(hod):
+    g = make_grid(5, 4, 3, 0.1, 2.0)
+    op = hod.Operator(g, tol_con=1e-6)
+    b = op.plane_wave(np.array([[0, 0, -1.0], [1.0, 0, 0]]))
+    b[:, 1] = 0
+    x, info = op.solve(b, tol=1e-5, use_precond=0)  # above the FP32 apply floor (~1e-7)
+    assert info["converged"].all()
+    assert torch.count_nonzero(x[:, 1]).item() == 0

@@ -1,0 +1,103 @@
+"""Host logic of the library (no GPU): exported symbols, argument checks, the KD tree
+and the sampled-row nested-ID construction, checked against the oracle."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import vie
+from oracle.tree import build_tree
+from synth.workloads import make_grid, small_case
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+_lib = pytest.importorskip("paper_2111_01730_amd._lib")
+if not os.path.exists(_lib.LIB_PATH):
+    pytest.skip("libhodbf.so not built", allow_module_level=True)
+from tests.plan_tools import hodbf_from_export  # noqa: E402
+
+
+def test_every_declared_symbol_is_exported():
+    header = open(os.path.join(ROOT, "include", "hodbf.h")).read()
+    names = set(re.findall(r"^\w[\w\s\*]*?\b(\w+)\s*\(", header, flags=re.M))
+    names = {n for n in names if n.startswith(("hodbf_", "vie_"))}
+    assert {"hodbf_build", "hodbf_apply", "hodbf_precond_apply", "vie_solve"} <= names
+    L = _lib.lib()
+    for n in sorted(names):
+        assert hasattr(L, n), n
+
+
+def _probe_all(grid, tol, seed=1):
+    p = _lib.make_params(grid, tol, seed=seed)
+    perm = _lib.probe(p, 0, np.int32)
+    table = _lib.probe(p, 1, np.int64).reshape(-1, 11)
+    vals = _lib.probe(p, 2, np.float64).view(np.complex128)
+    skel = _lib.probe(p, 6, np.int32)
+    return perm, table, vals, skel
+
+
+@pytest.mark.parametrize("sides", [(12, 10, 9), (8, 8, 8), (16, 16, 16), (5, 4, 3)])
+def test_library_tree_equals_oracle_kd(sides):
+    g = make_grid(*sides, 0.1, 2.0)
+    perm, *_ = _probe_all(g, 1e-4)
+    assert np.array_equal(perm, build_tree(g, 64).perm)
+
+
+def test_sampled_construction_accuracy_ragged():
+    c = small_case(31, sides=(12, 10, 9), h=0.1, eps_range=(2.0, 10.0), loss=1.0)
+    g = c["grid"]
+    op = hodbf_from_export(g, *_probe_all(g, 1e-4))
+    y = vie.dense(g) @ c["x"]
+    err = np.linalg.norm(op.apply(c["x"]) - y, axis=0) / np.linalg.norm(y, axis=0)
+    assert np.all(err <= 1e-3), err
+
+
+def test_sampled_construction_accuracy_c1_cube():
+    from synth import config
+    cfg = config("c1_plain_16")
+    g = cfg["grid"]
+    op = hodbf_from_export(g, *_probe_all(g, cfg["tol"]))
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal((g.n, 2)) + 1j * rng.standard_normal((g.n, 2))
+    y = vie.fft_matvec(g, x)
+    err = np.linalg.norm(op.apply(x) - y, axis=0) / np.linalg.norm(y, axis=0)
+    assert np.all(err <= 10 * cfg["tol"]), err
+
+
+def test_free_space_plan_has_zero_ranks():
+    g = make_grid(8, 8, 8, 0.125, 1.0)
+    perm, table, vals, skel = _probe_all(g, 1e-4)
+    assert np.all(table[:, 8] == 0)  # every stored factor has rank 0
+
+
+@pytest.mark.parametrize("field,value", [("nx", 0), ("h", 0.0), ("h", -1.0), ("k0", 0.0),
+                                         ("tol_con", 0.0), ("tol_con", 1.5), ("leaf_size", 0),
+                                         ("leaf_size", 65)])
+def test_argument_errors(field, value):
+    g = make_grid(4, 4, 4, 0.1, 2.0)
+    p = _lib.make_params(g, 1e-4)
+    setattr(p, field, value)
+    n = C.c_size_t(0)
+    code = _lib.lib().hodbf_plan_probe(C.byref(p), 0, None, C.byref(n))
+    assert code == -1
+    assert _lib.lib().hodbf_last_error()
+
+
+@pytest.mark.parametrize("bad", [0.0, np.nan, np.inf])
+def test_bad_permittivity(bad):
+    g = make_grid(4, 4, 4, 0.1, 2.0)
+    g.eps[7] = bad
+    p = _lib.make_params(g, 1e-4)
+    n = C.c_size_t(0)
+    assert _lib.lib().hodbf_plan_probe(C.byref(p), 0, None, C.byref(n)) == -1
+
+
+def test_null_arguments_rejected():
+    L = _lib.lib()
+    n = C.c_size_t(0)
+    assert L.hodbf_plan_probe(None, 0, None, C.byref(n)) == -1
+    assert L.hodbf_stats(None, None) == -1
+    assert L.hodbf_apply(None, 1, 0, None, 1, None, 1, None) == -1
+    L.hodbf_free(None)
