@@ -110,6 +110,18 @@ hodbf_status hodbf_precond_apply(const hodbf_op *op, int32_t nrhs, hodbf_dtype d
                                  const void *x, int64_t ldx, void *y, int64_t ldy,
                                  void *stream);
 
+/*
+ * hodbf_apply_tree -- the same products on vectors already in the library's internal
+ * layout: complex FP32, tree order (position t holds user index perm[t], see
+ * hodbf_export selector 0), right-hand sides interleaved, element (t, q) at
+ * ptr[t * nrhs + q].  which: 0 y = Z_con x; 1 y = P x with the default copy;
+ * 2 with the FP32 copy; 3 with the BF16 copy.  Only grouped-GEMM kernels run (no
+ * permutation), so callers that keep data in tree order avoid two passes.
+ * x and y must not overlap.  E_STATE if the requested factors are absent.
+ */
+hodbf_status hodbf_apply_tree(const hodbf_op *op, int32_t which, int32_t nrhs, const void *x,
+                              void *y, void *stream);
+
 typedef struct {
   double tol;           /* chi_sol: stop when ||b - Z x|| / ||b|| <= tol per column */
   int32_t restart;      /* GMRES restart length m, 1..200 (20 recommended) */

@@ -16,6 +16,7 @@ C64, C128 = 0, 1
 P_NONE, P_FP32, P_BF16, P_BOTH = 0, 1, 2, 3
 
 EXPORTED = ["hodbf_build", "hodbf_apply", "hodbf_precond_apply", "vie_solve", "hodbf_plane_wave",
+            "hodbf_apply_tree",
             "hodbf_stats", "hodbf_export", "hodbf_free", "hodbf_last_error", "hodbf_plan_probe"]
 
 
@@ -61,6 +62,9 @@ def lib():
     global _lib
     if _lib is not None:
         return _lib
+    # torch is the process's device-memory and stream provider: load its HIP runtime
+    # first so that the library binds to the same one
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_2111_01730_amd._build.build()")
     L = C.CDLL(LIB_PATH)
@@ -73,10 +77,11 @@ def lib():
     L.hodbf_stats.argtypes = [vp, C.POINTER(Stats)]
     L.hodbf_export.argtypes = [vp, i32, vp, C.POINTER(C.c_size_t)]
     L.hodbf_plan_probe.argtypes = [C.POINTER(BuildParams), i32, vp, C.POINTER(C.c_size_t)]
+    L.hodbf_apply_tree.argtypes = [vp, i32, i32, vp, vp, vp]
     L.hodbf_free.argtypes = [vp]
     L.hodbf_free.restype = None
     L.hodbf_last_error.restype = C.c_char_p
-    for name in ["hodbf_build", "hodbf_apply", "hodbf_precond_apply", "vie_solve",
+    for name in ["hodbf_build", "hodbf_apply", "hodbf_precond_apply", "vie_solve", "hodbf_apply_tree",
                  "hodbf_plane_wave", "hodbf_stats", "hodbf_export", "hodbf_plan_probe"]:
         getattr(L, name).restype = C.c_int
     _lib = L

@@ -1,6 +1,9 @@
 // C ABI of the hodbf library: construction, applies, export and error handling.
 #include <algorithm>
 #include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <functional>
@@ -17,6 +20,21 @@ static thread_local std::string g_last_error;
 void set_last_error(const std::string &msg) { g_last_error = msg; }
 
 [[noreturn]] void fail(hodbf_status code, const std::string &msg) { throw Error{code, msg}; }
+
+void logf(const char *fmt, ...) {
+  static const bool on = [] {
+    const char *e = std::getenv("HODBF_LOG");
+    return e && *e && std::strcmp(e, "0") != 0;
+  }();
+  if (!on) return;
+  va_list ap;
+  va_start(ap, fmt);
+  std::fprintf(stderr, "[hodbf] ");
+  std::vfprintf(stderr, fmt, ap);
+  std::fprintf(stderr, "\n");
+  std::fflush(stderr);
+  va_end(ap);
+}
 
 void hip_check(hipError_t e, const char *what) {
   if (e == hipSuccess) return;
@@ -197,6 +215,9 @@ hodbf_status hodbf_build(const hodbf_build_params *params, hodbf_op **out) {
     hipStream_t st = static_cast<hipStream_t>(params->stream);
     auto t0 = std::chrono::steady_clock::now();
     FwdPlan fp = build_forward_plan(*params);
+    logf("forward plan: N=%lld, L_H=%d, %lld IDs, max rank %d, %.2f s", (long long)fp.tree.n,
+         fp.tree.depth, (long long)fp.id_count, fp.max_rank,
+         std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
     std::unique_ptr<hodbf_op> op(new hodbf_op());
     op->params = *params;
     op->params.eps_r = nullptr;
@@ -278,6 +299,34 @@ hodbf_status hodbf_precond_apply(const hodbf_op *op, int32_t nrhs, hodbf_dtype d
     launch_scatter(zt, false, y, c128, ldy, op->dev.perm.as<int32_t>(), n, nrhs, st);
     HIPCHK(hipGetLastError());
     scratch_free(buf, st);
+  });
+}
+
+hodbf_status hodbf_apply_tree(const hodbf_op *op, int32_t which, int32_t nrhs, const void *x,
+                              void *y, void *stream) {
+  return guarded([&] {
+    if (!op || nrhs < 0 || which < 0 || which > 3) fail(HODBF_E_ARG, "bad operator, nrhs or which");
+    if (nrhs == 0) return;
+    if (!x || !y) fail(HODBF_E_ARG, "NULL vector");
+    const size_t vb = size_t(op->n) * nrhs * sizeof(float2);
+    const char *xb = static_cast<const char *>(x), *yb = static_cast<const char *>(y);
+    if (xb < yb + vb && yb < xb + vb) fail(HODBF_E_ARG, "x and y overlap");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int ft = FT_C64;
+    if (which > 0) {
+      if (!op->pre.present) fail(HODBF_E_STATE, "operator was built without a preconditioner");
+      ft = which == 1 ? op->pre.default_ft : (which == 2 ? FT_C64 : FT_BF16);
+      if (ft == FT_C64 && !op->pre.F32.p) fail(HODBF_E_STATE, "no FP32 preconditioner copy");
+      if (ft == FT_BF16 && !op->pre.BF16.p) fail(HODBF_E_STATE, "no BF16 preconditioner copy");
+    }
+    const int64_t rows = which == 0 ? forward_work_rows(*op) : precond_work_rows(*op);
+    float2 *wk = static_cast<float2 *>(scratch_alloc(size_t(std::max<int64_t>(rows, 1)) * nrhs * 8, st));
+    if (which == 0)
+      apply_forward_tree(*op, static_cast<const float2 *>(x), static_cast<float2 *>(y), wk, nrhs, st);
+    else
+      apply_precond_tree(*op, ft, static_cast<const float2 *>(x), static_cast<float2 *>(y), wk, nrhs, st);
+    HIPCHK(hipGetLastError());
+    scratch_free(wk, st);
   });
 }
 

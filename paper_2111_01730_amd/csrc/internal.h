@@ -19,6 +19,8 @@ struct Error {
 };
 [[noreturn]] void fail(hodbf_status code, const std::string &msg);
 void set_last_error(const std::string &msg);
+// Progress messages on stderr when the environment sets HODBF_LOG to a non-zero value.
+void logf(const char *fmt, ...) __attribute__((format(printf, 1, 2)));
 
 // ---------------------------------------------------------------------------
 // Geometry and cluster tree T_H (Section III-A), all arrays in tree order.

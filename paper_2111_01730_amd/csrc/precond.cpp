@@ -202,6 +202,9 @@ void build_precond(hodbf_op &op, hipStream_t st) {
     for (int64_t tau = 0; tau < (int64_t(1) << l); ++tau) {
       std::vector<cd> Xh;
       dense_x(op, rh, l, tau, Xh, st);
+      if (l <= 2)
+        logf("  dense X for level %d node %lld ready, %.2f s", l, (long long)tau,
+             std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
       DenseSource src;
       src.tree = &t;
       src.X = Xh.data();
@@ -254,6 +257,8 @@ void build_precond(hodbf_op &op, hipStream_t st) {
       md[2] = bf.ca;
       md[3] = bf.cb;
     });
+    logf("preconditioner level %d: %lld nodes, %.2f s so far", l, (long long)(int64_t(1) << l),
+         std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
     PrecondLevel lv;
     lv.level = l;
     upload_program(lv.prog, pk, st);

@@ -73,6 +73,17 @@ class Operator:
         """y = P x with P ~ Z^{-1}."""
         return self._call_apply(lib().hodbf_precond_apply, x)
 
+    def apply_tree(self, x: torch.Tensor, which: int = 0) -> torch.Tensor:
+        """Products on internal-layout vectors: x of shape (N, R) complex64 in tree order
+        (row t = user index perm[t]), contiguous, so element (t, q) sits at t*R + q.
+        which: 0 Z_con, 1 P (default copy), 2 P FP32 copy, 3 P BF16 copy."""
+        if x.dtype != torch.complex64 or not x.is_contiguous() or x.dim() != 2:
+            raise ValueError("x must be a contiguous (N, R) complex64 tensor")
+        y = torch.empty_like(x)
+        check(lib().hodbf_apply_tree(self._h, which, x.shape[1], C.c_void_p(x.data_ptr()),
+                                     C.c_void_p(y.data_ptr()), _stream()))
+        return y
+
     def plane_wave(self, dirs) -> torch.Tensor:
         d = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64).reshape(-1, 3))
         R = d.shape[0]
