@@ -2,15 +2,19 @@
 """Benchmark of the HOD-BF VIE hot path on one MI355X.
 
 One step = one preconditioned FGMRES solve of the whole right-hand-side batch to
-chi_sol (mixed precision: FP32 forward HOD-BF apply on MFMA, BF16 preconditioner with
-FP32 accumulation, FP64 Krylov arithmetic).  The workload is 32^3 = 32768 voxels in a
-4-wavelength cube, eps_r i.i.d. U[2, 10], 64 seeded plane waves, leaf 64, chi_con 1e-4.
+chi_sol: FP32 forward HOD-BF apply and FP32-stored preconditioner factors on MFMA with
+FP32 accumulation, FP64 Krylov arithmetic, 64 right-hand sides batched.  The workload
+is 32^3 = 32768 voxels in a 4-wavelength cube, eps_r i.i.d. U[2, 10], 64 seeded plane
+waves, leaf 64, chi_con 1e-4, chi_fact 1e-4, chi_sol 1e-4.
 
 Also measured (inputs resident in HBM, HIP events on the launch stream):
   * the forward apply alone: GFLOP/s = 8 * R * (stored complex entries) / time;
-  * the plain form: FP32 preconditioner, one right-hand side at a time;
-  * the oracle on the host CPU (FFT-exact operator, unpreconditioned FGMRES, one column).
-Prints one JSON line.
+  * the plain form: FP32 everything, one right-hand side at a time;
+  * the same batched solve with the FP16 and BF16 copies of the preconditioner;
+  * the oracle on the host CPU (a bounded sample of FGMRES steps, see cpu_baseline).
+``--mode apply`` builds only the forward operator and runs forward applies (and one
+device copy of known size, the reference for traffic counters); it is the profiled
+command.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -55,12 +59,49 @@ def cpu_baseline_leg(seconds: float) -> dict:
     return dict(seconds=t, steps=k, sec_per_step=t / k)
 
 
+def apply_mode(args, cfg, Operator, P_NONE):
+    """Forward operator only: one device copy of known size, then forward applies."""
+    import numpy as np
+    import torch
+    g = cfg["grid"]
+    R = cfg["nrhs"]
+    op = Operator(g, tol_con=cfg["tol"], precond=P_NONE, seed=cfg["seed"])
+    st = op.stats()
+    b = op.plane_wave(cfg["dirs"])
+    perm = torch.as_tensor(op.perm().astype(np.int64), device="cuda")
+    xt = b[perm].to(torch.complex64).contiguous()
+    ref = torch.empty(64 << 20, dtype=torch.float32, device="cuda")  # 256 MiB copy reference
+    dst = torch.empty_like(ref)
+    for _ in range(3):
+        dst.copy_(ref)
+    torch.cuda.synchronize()
+    reps = max(1, args.steps)
+    for _ in range(args.warmup):
+        op.apply_tree(xt, 0)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        op.apply_tree(xt, 0)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / reps * 1e-3
+    fl = 8.0 * R * st["entries_fwd"]
+    print(json.dumps({"mode": "apply", "apply_ms": t * 1e3, "apply_gflops": fl / t / 1e9,
+                      "launches_per_apply": st["fwd_stages"], "entries_fwd": st["entries_fwd"],
+                      "reps": reps, "copy_bytes": ref.numel() * 4}), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--tol-fact", type=float, default=1e-2)
+    ap.add_argument("--tol-fact", type=float, default=1e-4)
+    ap.add_argument("--mode", choices=["solve", "apply"], default="solve")
+    ap.add_argument("--variant-max-iter", type=int, default=300)
     ap.add_argument("--plain-rhs", type=int, default=4, help="columns timed in the plain form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-baseline-leg", action="store_true", help=argparse.SUPPRESS)
@@ -78,15 +119,18 @@ def main():
     import numpy as np
     import torch
 
-    from paper_2111_01730_amd.hodbf import P_BOTH, Operator
+    from paper_2111_01730_amd.hodbf import P_BF16, P_FP16, P_FP32, P_NONE, Operator
     from synth import config
 
     torch.cuda.set_device(0)
     cfg = config(WORKLOAD)
     g = cfg["grid"]
     R = cfg["nrhs"]
+    if args.mode == "apply":
+        return apply_mode(args, cfg, Operator, P_NONE)
     t0 = time.perf_counter()
-    op = Operator(g, tol_con=cfg["tol"], tol_fact=args.tol_fact, precond=P_BOTH, seed=cfg["seed"])
+    op = Operator(g, tol_con=cfg["tol"], tol_fact=args.tol_fact, precond=P_FP32 | P_BF16 | P_FP16,
+                  seed=cfg["seed"])
     build_s = time.perf_counter() - t0
     st = op.stats()
     log(f"[build] {build_s:.1f}s stats={st}")
@@ -108,29 +152,43 @@ def main():
         return e0.elapsed_time(e1) / reps * 1e-3
 
     t_fwd = time_apply(0, args.apply_reps)
-    t_pre_bf16 = time_apply(3, args.apply_reps)
-    t_pre_fp32 = time_apply(2, args.apply_reps)
+    t_pre = {c: time_apply(w, args.apply_reps) for c, w in (("fp32", 2), ("fp16", 4), ("bf16", 3))}
     flops_fwd = 8.0 * R * st["entries_fwd"]
-    log(f"[apply] fwd {t_fwd * 1e3:.3f} ms ({flops_fwd / t_fwd / 1e9:.1f} GFLOP/s), "
-        f"precond bf16 {t_pre_bf16 * 1e3:.3f} ms, fp32 {t_pre_fp32 * 1e3:.3f} ms")
+    log(f"[apply] fwd {t_fwd * 1e3:.3f} ms ({flops_fwd / t_fwd / 1e9:.1f} GFLOP/s), precond "
+        + ", ".join(f"{c} {t * 1e3:.3f} ms" for c, t in t_pre.items()))
 
     # warmup solves
     for _ in range(args.warmup):
-        _, info = op.solve(b, tol=TOL_SOL, use_precond="bf16")
+        _, info = op.solve(b, tol=TOL_SOL, use_precond="fp32")
     torch.cuda.synchronize()
     iters = []
     conv = True
     torch.cuda.synchronize()
     ts = time.perf_counter()
     for _ in range(args.steps):
-        x, info = op.solve(b, tol=TOL_SOL, use_precond="bf16")
+        x, info = op.solve(b, tol=TOL_SOL, use_precond="fp32")
         iters.append(int(info["iters"].max()))
         conv = conv and bool(info["converged"].all())
     torch.cuda.synchronize()
     t_step = (time.perf_counter() - ts) / args.steps
     solves_per_s = R / t_step
-    log(f"[solve mixed] {t_step * 1e3:.1f} ms/step, iters max {iters}, converged {conv}, "
-        f"relres max {info['relres'].max():.2e}")
+    iters_mean = float(info["iters"].mean())
+    log(f"[solve batched fp32] {t_step * 1e3:.1f} ms/step, iters max {iters}, mean {iters_mean:.1f}, "
+        f"converged {conv}, relres max {info['relres'].max():.2e}")
+
+    # the reduced-precision preconditioner copies on the same batch (bounded)
+    variants = {}
+    for c in ("fp16", "bf16"):
+        torch.cuda.synchronize()
+        tv = time.perf_counter()
+        _, vi = op.solve(b, tol=TOL_SOL, use_precond=c, max_iter=args.variant_max_iter)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - tv
+        variants[c] = {"converged": bool(vi["converged"].all()), "iters_max": int(vi["iters"].max()),
+                       "iters_mean": float(vi["iters"].mean()), "relres_max": float(vi["relres"].max()),
+                       "seconds": dt, "solves_per_s": (R / dt) if vi["converged"].all() else 0.0,
+                       "precond_apply_ms": t_pre[c] * 1e3}
+        log(f"[solve batched {c}] {variants[c]}")
 
     # plain form: FP32 preconditioner, one column at a time
     npl = min(args.plain_rhs, R)
@@ -152,14 +210,14 @@ def main():
                            capture_output=True, text=True, env=env, timeout=600)
         leg = json.loads(r.stdout.strip().splitlines()[-1])
         log(f"[cpu oracle] {leg}")
-        per_col = float(np.mean([int(v) for v in info["iters"]]))
+        per_col = iters_mean
         cpu = {"value": 1.0 / (leg["sec_per_step"] * per_col), "unit": "solves/s", "cores": 1,
                "kind": "oracle",
                "sample": (f"{leg['steps']} FGMRES(20) Arnoldi steps of the oracle (FFT-exact "
                           f"product + modified Gram-Schmidt, complex FP64) on plane wave 0 of this "
                           f"workload in {leg['seconds']:.1f} s = {leg['sec_per_step'] * 1e3:.1f} ms/step; "
                           f"solves/s = 1 / (ms/step x {per_col:.1f} steps per column, the mean "
-                          f"iteration count of the GPU mixed solve)")}
+                          f"iteration count of the GPU batched solve)")}
 
     ach = flops_fwd / t_fwd / 1e12
     out = {
@@ -173,19 +231,20 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 apply / bf16 precond / f64 krylov",
+        "dtype": "f32 apply / f32 precond / f64 krylov",
         "data": "synthetic",
         "config": {"workload": "32^3 voxels, 4-wavelength cube, eps_r iid U[2,10], 64 plane waves",
                    "n": g.n, "nrhs": R, "leaf": 64, "tol_con": cfg["tol"],
                    "tol_fact": args.tol_fact, "tol_sol": TOL_SOL, "parallelism": "1 GPU"},
         "apply_gflops": flops_fwd / t_fwd / 1e9,
         "apply_ms": t_fwd * 1e3,
-        "precond_apply_ms_bf16": t_pre_bf16 * 1e3,
-        "precond_apply_ms_fp32": t_pre_fp32 * 1e3,
-        "mixed_solves_per_s": solves_per_s,
+        "precond_apply_ms_fp32": t_pre["fp32"] * 1e3,
+        "batched_solves_per_s": solves_per_s,
         "plain_fp32_solves_per_s": plain_solves_per_s,
-        "mixed_vs_plain": solves_per_s / plain_solves_per_s,
-        "iters_mixed_max": max(iters),
+        "batched_vs_plain": solves_per_s / plain_solves_per_s,
+        "reduced_precision_precond": variants,
+        "iters_batched_max": max(iters),
+        "iters_batched_mean": iters_mean,
         "iters_plain": plain_iters,
         "converged": conv,
         "build_s": build_s,

@@ -51,12 +51,21 @@ typedef enum {
 
 typedef enum { HODBF_C64 = 0, HODBF_C128 = 1 } hodbf_dtype; /* complex FP32 / FP64 */
 
-/* Storage precision of the preconditioner's factors (applies accumulate in FP32). */
+/*
+ * Storage precision of the preconditioner's factors, a bit mask: every copy asked for
+ * is kept (same structure, values rounded from one FP64 construction) and a solve
+ * or apply can pick any of them.  Applies accumulate in FP32.
+ *   FP32: complex FP32 factors, FP32 MFMA.
+ *   BF16: complex BF16 factors and BF16-rounded inputs, BF16 MFMA.
+ *   FP16: complex FP16 factors (each block scaled by its largest magnitude),
+ *         converted to FP32 on load, FP32 MFMA.
+ */
 typedef enum {
   HODBF_P_NONE = 0, /* no preconditioner */
   HODBF_P_FP32 = 1,
   HODBF_P_BF16 = 2,
-  HODBF_P_BOTH = 3  /* keep FP32 and BF16 copies (select per solve) */
+  HODBF_P_BOTH = 3, /* FP32 | BF16 */
+  HODBF_P_FP16 = 4
 } hodbf_prec;
 
 /*
@@ -72,7 +81,7 @@ typedef struct {
   double tol_con;        /* chi_con in (0, 1): ID truncation of the forward operator */
   double tol_fact;       /* chi_fact in (0, 1): ID truncation of the inverse factors */
   int32_t leaf_size;     /* leaf cluster size of T_H, 1..64 (64 recommended) */
-  int32_t precond_prec;  /* hodbf_prec */
+  int32_t precond_prec;  /* hodbf_prec bit mask, 0..7 */
   int32_t precond_min_level; /* levels < this get no X_tau (0 = full Algorithm 1 form) */
   uint64_t seed;         /* row-sampling RNG seed */
   size_t hbm_budget;     /* bytes of device memory the operator may hold; 0 = unlimited */
@@ -103,8 +112,8 @@ hodbf_status hodbf_apply(const hodbf_op *op, int32_t nrhs, hodbf_dtype dtype,
 /*
  * hodbf_precond_apply -- y = P x with P ~ Z^{-1}: the leaf inverses D_tau^{-1}
  * followed, level by level towards the root, by z(tau) <- (I + X_tau) z(tau)
- * (Algorithm 1 unrolled).  Factors in the operator's stored precision (BF16 if
- * present, else FP32), FP32 accumulation.  E_STATE if built without one.
+ * (Algorithm 1 unrolled).  Uses the default copy: FP16 if stored, else FP32, else
+ * BF16.  FP32 accumulation.  E_STATE if built without one.
  */
 hodbf_status hodbf_precond_apply(const hodbf_op *op, int32_t nrhs, hodbf_dtype dtype,
                                  const void *x, int64_t ldx, void *y, int64_t ldy,
@@ -115,7 +124,7 @@ hodbf_status hodbf_precond_apply(const hodbf_op *op, int32_t nrhs, hodbf_dtype d
  * layout: complex FP32, tree order (position t holds user index perm[t], see
  * hodbf_export selector 0), right-hand sides interleaved, element (t, q) at
  * ptr[t * nrhs + q].  which: 0 y = Z_con x; 1 y = P x with the default copy;
- * 2 with the FP32 copy; 3 with the BF16 copy.  Only grouped-GEMM kernels run (no
+ * 2 with the FP32 copy; 3 with the BF16 copy; 4 with the FP16 copy.  Only grouped-GEMM kernels run (no
  * permutation), so callers that keep data in tree order avoid two passes.
  * x and y must not overlap.  E_STATE if the requested factors are absent.
  */
@@ -126,7 +135,7 @@ typedef struct {
   double tol;           /* chi_sol: stop when ||b - Z x|| / ||b|| <= tol per column */
   int32_t restart;      /* GMRES restart length m, 1..200 (20 recommended) */
   int32_t max_iter;     /* cap on Arnoldi steps per column (the paper caps at 3000) */
-  int32_t use_precond;  /* 0: none; 1: operator default; HODBF_P_FP32 / HODBF_P_BF16 + 8 */
+  int32_t use_precond;  /* 0: none; 1: operator default; 8 + HODBF_P_FP32 / _BF16 / _FP16 */
 } hodbf_solve_opts;
 
 typedef struct {
@@ -180,9 +189,9 @@ hodbf_status hodbf_stats(const hodbf_op *op, hodbf_stats_t *st);
  * hodbf_export -- copy operator internals to HOST memory for verification.
  * which: 0 perm (int32 N: tree position -> user index);
  *        1 forward block table, 2 forward factor values (complex FP32),
- *        3 preconditioner block table, 4 preconditioner values (complex FP32,
- *          converted from the stored precision, FP32 copy if both are stored),
- *        5 preconditioner values of the BF16 copy (converted to complex FP32).
+ *        3 preconditioner block table, 4 preconditioner values of the FP32 copy,
+ *        5 of the BF16 copy, 6 of the FP16 copy (each as complex FP32, block
+ *          scales applied).
  * Block tables are int64 rows of 11: kind (0 dense leaf, 1 V0, 2 W, 3 B),
  * hod level l, node i, child row ca, child col cb, butterfly level, a, b, rows m,
  * cols n, offset (complex elements into the values, column-major m x n).

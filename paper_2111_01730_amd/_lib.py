@@ -13,7 +13,7 @@ HODBF_OK = 0
 STATUS = {0: "OK", -1: "E_ARG", -2: "E_NOMEM", -3: "E_HIP", -4: "E_NUMERIC", -5: "E_NOCONV",
           -6: "E_STATE"}
 C64, C128 = 0, 1
-P_NONE, P_FP32, P_BF16, P_BOTH = 0, 1, 2, 3
+P_NONE, P_FP32, P_BF16, P_BOTH, P_FP16 = 0, 1, 2, 3, 4
 
 EXPORTED = ["hodbf_build", "hodbf_apply", "hodbf_precond_apply", "vie_solve", "hodbf_plane_wave",
             "hodbf_apply_tree",

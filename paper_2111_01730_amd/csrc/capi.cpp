@@ -119,7 +119,7 @@ int64_t precond_work_rows(const hodbf_op &op) {
 
 void apply_precond_tree(const hodbf_op &op, int ftype, const float2 *x, float2 *z, float2 *work,
                         int R, hipStream_t st) {
-  const void *F = ftype == FT_BF16 ? op.pre.BF16.p : op.pre.F32.p;
+  const void *F = ftype == FT_BF16 ? op.pre.BF16.p : (ftype == FT_F16 ? op.pre.F16.p : op.pre.F32.p);
   // z = blockdiag(D_leaf^{-1}) x, then z(tau) += X_tau z(tau) level by level to the root
   run_program(op.pre.leaf, F, ftype, x, work, z, R, st);
   for (const PrecondLevel &lv : op.pre.levels) run_program(lv.prog, F, ftype, z, work, z, R, st);
@@ -151,7 +151,8 @@ static void pack_forward(hodbf_op &op, FwdPlan &fp, hipStream_t st) {
   std::vector<int32_t> jobcols;
   PackSink pk;
   pk.table = &op.fwd_table;
-  pk.put_host = [&](const Mat &f) -> int64_t {
+  pk.put_host = [&](const Mat &f, float *scale) -> int64_t {
+    *scale = 1.0f;
     const int64_t off = align16(int64_t(host.size()));
     host.resize(size_t(off + int64_t(f.m) * f.n), make_float2(0.f, 0.f));
     for (size_t e = 0; e < f.v.size(); ++e)
@@ -305,7 +306,7 @@ hodbf_status hodbf_precond_apply(const hodbf_op *op, int32_t nrhs, hodbf_dtype d
 hodbf_status hodbf_apply_tree(const hodbf_op *op, int32_t which, int32_t nrhs, const void *x,
                               void *y, void *stream) {
   return guarded([&] {
-    if (!op || nrhs < 0 || which < 0 || which > 3) fail(HODBF_E_ARG, "bad operator, nrhs or which");
+    if (!op || nrhs < 0 || which < 0 || which > 4) fail(HODBF_E_ARG, "bad operator, nrhs or which");
     if (nrhs == 0) return;
     if (!x || !y) fail(HODBF_E_ARG, "NULL vector");
     const size_t vb = size_t(op->n) * nrhs * sizeof(float2);
@@ -315,9 +316,10 @@ hodbf_status hodbf_apply_tree(const hodbf_op *op, int32_t which, int32_t nrhs, c
     int ft = FT_C64;
     if (which > 0) {
       if (!op->pre.present) fail(HODBF_E_STATE, "operator was built without a preconditioner");
-      ft = which == 1 ? op->pre.default_ft : (which == 2 ? FT_C64 : FT_BF16);
+      ft = which == 1 ? op->pre.default_ft : (which == 2 ? FT_C64 : (which == 3 ? FT_BF16 : FT_F16));
       if (ft == FT_C64 && !op->pre.F32.p) fail(HODBF_E_STATE, "no FP32 preconditioner copy");
       if (ft == FT_BF16 && !op->pre.BF16.p) fail(HODBF_E_STATE, "no BF16 preconditioner copy");
+      if (ft == FT_F16 && !op->pre.F16.p) fail(HODBF_E_STATE, "no FP16 preconditioner copy");
     }
     const int64_t rows = which == 0 ? forward_work_rows(*op) : precond_work_rows(*op);
     float2 *wk = static_cast<float2 *>(scratch_alloc(size_t(std::max<int64_t>(rows, 1)) * nrhs * 8, st));
@@ -361,7 +363,7 @@ hodbf_status hodbf_stats(const hodbf_op *op, hodbf_stats_t *s) {
     s->entries_fwd = op->fwd_entries;
     s->entries_pre = op->pre.entries;
     s->bytes_fwd = int64_t(op->fwdF.bytes);
-    s->bytes_pre = int64_t(op->pre.F32.bytes + op->pre.BF16.bytes);
+    s->bytes_pre = int64_t(op->pre.F32.bytes + op->pre.BF16.bytes + op->pre.F16.bytes);
     s->bytes_total = s->bytes_fwd + s->bytes_pre + int64_t(op->fwd.segs.bytes + op->fwd.pairs.bytes) +
                      int64_t(op->dev.perm.bytes + op->dev.xyz.bytes + op->dev.inv_eps.bytes +
                              op->dev.kappa.bytes);
@@ -385,26 +387,62 @@ static void export_bytes(const void *src, size_t n, void *buf, size_t *bytes) {
   *bytes = n;
 }
 
-static void export_arena(const DevBuf &a, bool bf16, void *buf, size_t *bytes) {
-  const size_t count = bf16 ? a.bytes / 4 : a.bytes / 8;
+static float f16_to_f32(uint32_t h) {
+  const uint32_t sign = (h & 0x8000u) << 16, e = (h >> 10) & 0x1F, m = h & 0x3FFu;
+  uint32_t x;
+  if (e == 0) {
+    if (m == 0) x = sign;
+    else {  // subnormal: value m * 2^-24
+      float f = float(m) * 5.9604644775390625e-8f;
+      std::memcpy(&x, &f, 4);
+      x |= sign;
+    }
+  } else if (e == 31) {
+    x = sign | 0x7F800000u | (m << 13);
+  } else {
+    x = sign | ((e - 15 + 127) << 23) | (m << 13);
+  }
+  float f;
+  std::memcpy(&f, &x, 4);
+  return f;
+}
+
+// ft: FT_C64 / FT_BF16 / FT_F16 storage; scales (per table row) restore block values.
+static void export_arena(const DevBuf &a, int ft, const std::vector<BlockRec> *table,
+                         const std::vector<float> *scales, void *buf, size_t *bytes) {
+  const size_t count = ft == FT_C64 ? a.bytes / 8 : a.bytes / 4;
   const size_t need = count * sizeof(float) * 2;
   if (!buf) {
     *bytes = need;
     return;
   }
   if (*bytes < need) fail(HODBF_E_ARG, "export buffer too small");
-  if (!bf16) {
+  float *o = static_cast<float *>(buf);
+  if (ft == FT_C64) {
     HIPCHK(hipMemcpy(buf, a.p, need, hipMemcpyDeviceToHost));
   } else {
     std::vector<uint32_t> tmp(count);
     HIPCHK(hipMemcpy(tmp.data(), a.p, count * 4, hipMemcpyDeviceToHost));
-    float *o = static_cast<float *>(buf);
     for (size_t i = 0; i < count; ++i) {
-      uint32_t lo = (tmp[i] & 0xFFFFu) << 16, hi = tmp[i] & 0xFFFF0000u;
-      std::memcpy(o + 2 * i, &lo, 4);
-      std::memcpy(o + 2 * i + 1, &hi, 4);
+      if (ft == FT_BF16) {
+        uint32_t lo = (tmp[i] & 0xFFFFu) << 16, hi = tmp[i] & 0xFFFF0000u;
+        std::memcpy(o + 2 * i, &lo, 4);
+        std::memcpy(o + 2 * i + 1, &hi, 4);
+      } else {
+        o[2 * i] = f16_to_f32(tmp[i] & 0xFFFFu);
+        o[2 * i + 1] = f16_to_f32(tmp[i] >> 16);
+      }
     }
   }
+  if (table && scales)
+    for (size_t r = 0; r < table->size(); ++r) {
+      const BlockRec &b = (*table)[r];
+      const float s = (*scales)[r];
+      for (int64_t e = 0; e < b.m * b.n; ++e) {
+        o[2 * (b.off + e)] *= s;
+        o[2 * (b.off + e) + 1] *= s;
+      }
+    }
   *bytes = need;
 }
 
@@ -419,19 +457,20 @@ hodbf_status hodbf_export(const hodbf_op *op, int32_t which, void *buf, size_t *
         export_bytes(op->fwd_table.data(), op->fwd_table.size() * sizeof(BlockRec), buf, bytes);
         break;
       case 2:
-        export_arena(op->fwdF, false, buf, bytes);
+        export_arena(op->fwdF, FT_C64, nullptr, nullptr, buf, bytes);
         break;
       case 3:
         export_bytes(op->pre.table.data(), op->pre.table.size() * sizeof(BlockRec), buf, bytes);
         break;
       case 4:
-        if (op->pre.F32.p) export_arena(op->pre.F32, false, buf, bytes);
-        else export_arena(op->pre.BF16, true, buf, bytes);
-        break;
       case 5:
-        if (!op->pre.BF16.p) fail(HODBF_E_STATE, "no BF16 preconditioner copy");
-        export_arena(op->pre.BF16, true, buf, bytes);
+      case 6: {
+        const DevBuf &a = which == 4 ? op->pre.F32 : (which == 5 ? op->pre.BF16 : op->pre.F16);
+        if (!a.p) fail(HODBF_E_STATE, "that preconditioner copy is not stored");
+        export_arena(a, which == 4 ? FT_C64 : (which == 5 ? FT_BF16 : FT_F16), &op->pre.table,
+                     &op->pre.scales, buf, bytes);
         break;
+      }
       default:
         fail(HODBF_E_ARG, "unknown export selector");
     }

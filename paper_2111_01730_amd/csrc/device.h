@@ -13,11 +13,14 @@ struct Seg {
   int32_t out_row, m, p0, p1;
 };
 
-// A factor block (column-major, element (i, k) at f_off + k * lda + i) times the
-// input rows [in_row, in_row + n) of buffer X (in_buf = 0) or T (in_buf = 1).
+// A factor block (column-major, element (i, k) at f_off + k * lda + i, stored values
+// multiplied by scale on load) times the input rows [in_row, in_row + n) of buffer X
+// (in_buf = 0) or T (in_buf = 1).
 struct Pair {
   int64_t f_off;
   int32_t in_row, n, lda, in_buf;
+  float scale;
+  int32_t pad;
 };
 
 // Device entry-generation job: column-major block of Z, rows r0..r0+m (tree order,
@@ -27,7 +30,9 @@ struct EntryJob {
   int32_t r0, m, c_off, n;
 };
 
-enum FactorType { FT_C64 = 0, FT_BF16 = 1 };
+// Factor storage: complex FP32; complex BF16 (BF16 MFMA arithmetic); complex FP16
+// (converted to FP32 on load, FP32 MFMA arithmetic).
+enum FactorType { FT_C64 = 0, FT_BF16 = 1, FT_F16 = 2 };
 
 // Grouped GEMM over segs[s0, s0 + ns): OUT(seg rows) = beta * OUT + sum A * in.
 // X, T, OUT: complex FP32 RHS-interleaved (element (row, q) at row * R + q).

@@ -41,6 +41,9 @@ static void solve_impl(const hodbf_op &op, int R, const void *b, int64_t ldb, vo
   } else if (o.use_precond == 8 + HODBF_P_BF16) {
     if (!op.pre.BF16.p) fail(HODBF_E_STATE, "no BF16 preconditioner copy");
     pre_ft = FT_BF16;
+  } else if (o.use_precond == 8 + HODBF_P_FP16) {
+    if (!op.pre.F16.p) fail(HODBF_E_STATE, "no FP16 preconditioner copy");
+    pre_ft = FT_F16;
   } else if (o.use_precond != 0) {
     fail(HODBF_E_ARG, "unknown use_precond");
   }

@@ -1,5 +1,6 @@
 // HIP kernels for gfx950: entry generation, permutation, and the grouped complex GEMM
 // that applies every butterfly factor stage and the leaf / outer blocks.
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -65,12 +66,24 @@ void launch_entries(const EntryJob *jobs, int64_t njobs, const int32_t *cols, co
 }
 
 // ---------------------------------------------------------------------------
-// Factor element loads: complex FP32, or complex BF16 packed as (re | im << 16).
+// Factor element loads: complex FP32, or a complex pair of 16-bit values packed as
+// (re | im << 16) in BF16 or IEEE FP16.
+struct FBF16 {
+  uint32_t v;
+};
+struct FF16 {
+  uint32_t v;
+};
 __device__ inline float2 load_factor(const float2 *F, int64_t idx) { return F[idx]; }
 __device__ inline float bf16_to_f(uint32_t h) { return __uint_as_float(h << 16); }
-__device__ inline float2 load_factor(const uint32_t *F, int64_t idx) {
-  const uint32_t w = F[idx];
+__device__ inline float2 load_factor(const FBF16 *F, int64_t idx) {
+  const uint32_t w = F[idx].v;
   return make_float2(bf16_to_f(w & 0xFFFFu), bf16_to_f(w >> 16));
+}
+__device__ inline float2 load_factor(const FF16 *F, int64_t idx) {
+  const uint32_t w = F[idx].v;
+  return make_float2(__half2float(__ushort_as_half((unsigned short)(w & 0xFFFFu))),
+                     __half2float(__ushort_as_half((unsigned short)(w >> 16))));
 }
 
 // Small-R grouped GEMM: one wave per segment.  Lanes split the m <= 64 rows and a few
@@ -98,8 +111,10 @@ __global__ __launch_bounds__(256) void k_grouped_gemv(const Seg *__restrict__ se
       const Pair pr = pairs[p];
       const float2 *in = (pr.in_buf ? T : X) + int64_t(pr.in_row) * R + q0;
       for (int k = g; k < pr.n; k += G) {
-        const float2 a = i < m ? load_factor(F, pr.f_off + int64_t(k) * pr.lda + i)
-                               : make_float2(0.f, 0.f);
+        float2 a = i < m ? load_factor(F, pr.f_off + int64_t(k) * pr.lda + i)
+                         : make_float2(0.f, 0.f);
+        a.x *= pr.scale;
+        a.y *= pr.scale;
         const float2 *xk = in + int64_t(k) * R;
 #pragma unroll
         for (int qq = 0; qq < 4; ++qq) {
@@ -144,9 +159,10 @@ __global__ __launch_bounds__(256) void k_grouped_gemv(const Seg *__restrict__ se
 // MFMAs consume 8 complex columns: slot kk of MFMA t is real column 4 kk + t, i.e.
 // complex column 2 kk + t / 2, part t % 2.  Each workgroup owns one segment (<= 64
 // rows = 4 row tiles); its waves split row tiles and 8-RHS column tiles.
+template <typename FT>
 __global__ __launch_bounds__(256) void k_grouped_mfma_f32(const Seg *__restrict__ segs,
                                                           const Pair *__restrict__ pairs,
-                                                          const float2 *__restrict__ F,
+                                                          const FT *__restrict__ F,
                                                           const float2 *__restrict__ X,
                                                           const float2 *__restrict__ T,
                                                           float2 *__restrict__ OUT, int R,
@@ -172,15 +188,20 @@ __global__ __launch_bounds__(256) void k_grouped_mfma_f32(const Seg *__restrict_
     for (int j = 0; j < 8; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
     for (int p = sg.p0; p < sg.p1; ++p) {
       const Pair pr = pairs[p];
-      const float2 *A = F + pr.f_off;
+      const FT *A = F + pr.f_off;
       const float2 *in = (pr.in_buf ? T : X) + int64_t(pr.in_row) * R;
       const int n = pr.n;
+      const float sc = pr.scale;
       for (int c0 = 0; c0 < n; c0 += 8) {
         const int c = c0 + 2 * kk;
         const bool rok = ia < m;
         const float2 z2 = make_float2(0.f, 0.f);
-        const float2 a0 = (rok && c < n) ? A[int64_t(c) * pr.lda + ia] : z2;
-        const float2 a1 = (rok && c + 1 < n) ? A[int64_t(c + 1) * pr.lda + ia] : z2;
+        float2 a0 = (rok && c < n) ? load_factor(A, int64_t(c) * pr.lda + ia) : z2;
+        float2 a1 = (rok && c + 1 < n) ? load_factor(A, int64_t(c + 1) * pr.lda + ia) : z2;
+        a0.x *= sc;
+        a0.y *= sc;
+        a1.x *= sc;
+        a1.y *= sc;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
           const int nt = sub + j * wpr;
@@ -262,6 +283,7 @@ __global__ __launch_bounds__(256) void k_grouped_mfma_bf16(const Seg *__restrict
       const uint32_t *A = F + pr.f_off;
       const float2 *in = (pr.in_buf ? T : X) + int64_t(pr.in_row) * R;
       const int n = pr.n;
+      const float sc = pr.scale;  // applied to the inputs: the BF16 MFMA has no per-pair scale
       for (int c0 = 0; c0 < n; c0 += 8) {
         const int c = c0 + 2 * kk;
         const bool rok = ia < m;
@@ -279,8 +301,12 @@ __global__ __launch_bounds__(256) void k_grouped_mfma_bf16(const Seg *__restrict
           if (nt < nnt) {
             const int q = q0 + nt * 8 + qo;
             const bool qok = q < R;
-            const float2 x0 = (qok && c < n) ? in[int64_t(c) * R + q] : z2;
-            const float2 x1 = (qok && c + 1 < n) ? in[int64_t(c + 1) * R + q] : z2;
+            float2 x0 = (qok && c < n) ? in[int64_t(c) * R + q] : z2;
+            float2 x1 = (qok && c + 1 < n) ? in[int64_t(c + 1) * R + q] : z2;
+            x0.x *= sc;
+            x0.y *= sc;
+            x1.x *= sc;
+            x1.y *= sc;
             shortx4 bv;
             bv[0] = f_to_bf16(op ? x0.y : x0.x);
             bv[1] = f_to_bf16(op ? x0.x : -x0.y);
@@ -321,14 +347,20 @@ void launch_grouped(const Seg *segs, const Pair *pairs, int64_t s0, int64_t ns, 
     if (ftype == FT_C64)
       hipLaunchKernelGGL(k_grouped_gemv<float2>, dim3(unsigned(nb)), dim3(256), 0, st, sp, pairs,
                          static_cast<const float2 *>(F), X, T, OUT, R, beta, ns);
+    else if (ftype == FT_BF16)
+      hipLaunchKernelGGL(k_grouped_gemv<FBF16>, dim3(unsigned(nb)), dim3(256), 0, st, sp,
+                         pairs, static_cast<const FBF16 *>(F), X, T, OUT, R, beta, ns);
     else
-      hipLaunchKernelGGL(k_grouped_gemv<uint32_t>, dim3(unsigned(nb)), dim3(256), 0, st, sp,
-                         pairs, static_cast<const uint32_t *>(F), X, T, OUT, R, beta, ns);
+      hipLaunchKernelGGL(k_grouped_gemv<FF16>, dim3(unsigned(nb)), dim3(256), 0, st, sp,
+                         pairs, static_cast<const FF16 *>(F), X, T, OUT, R, beta, ns);
     return;
   }
   if (ftype == FT_C64)
-    hipLaunchKernelGGL(k_grouped_mfma_f32, dim3(unsigned(ns)), dim3(256), 0, st, sp, pairs,
+    hipLaunchKernelGGL(k_grouped_mfma_f32<float2>, dim3(unsigned(ns)), dim3(256), 0, st, sp, pairs,
                        static_cast<const float2 *>(F), X, T, OUT, R, beta);
+  else if (ftype == FT_F16)
+    hipLaunchKernelGGL(k_grouped_mfma_f32<FF16>, dim3(unsigned(ns)), dim3(256), 0, st, sp, pairs,
+                       static_cast<const FF16 *>(F), X, T, OUT, R, beta);
   else
     hipLaunchKernelGGL(k_grouped_mfma_bf16, dim3(unsigned(ns)), dim3(256), 0, st, sp, pairs,
                        static_cast<const uint32_t *>(F), X, T, OUT, R, beta);

@@ -71,7 +71,8 @@ struct PrecondLevel {
 struct PrecondData {
   bool present = false;
   int min_level = 0;
-  DevBuf F32, BF16;          // factor arenas (FP32 and / or BF16 complex)
+  DevBuf F32, BF16, F16;     // factor arenas (complex FP32 / BF16 / FP16), same offsets
+  std::vector<float> scales; // load scale of every table row
   Program leaf;              // z = D_leaf^{-1} x
   std::vector<PrecondLevel> levels;  // from level L_H - 1 towards min_level
   std::vector<BlockRec> table;

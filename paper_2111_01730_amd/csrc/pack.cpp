@@ -57,7 +57,7 @@ void pack_group(PackSink &pk, const Tree &t, const std::vector<const Butterfly *
           off[k][s][size_t(a * nb + b)] = out_row;
           pk.t_rows += f.m;
           if (f.m == 0 || f.n == 0) continue;
-          Pair p;
+          Pair p{};
           p.lda = f.m;
           p.n = f.n;
           if (s == 0) {
@@ -68,9 +68,10 @@ void pack_group(PackSink &pk, const Tree &t, const std::vector<const Butterfly *
             p.in_buf = 1;
             p.in_row = int32_t(off[k][s - 1][size_t((a / 2) * 2 * nb + 2 * b)]);
           }
-          p.f_off = pk.put_host(f);
+          p.f_off = pk.put_host(f, &p.scale);
           pk.table->push_back({s == 0 ? 1 : 2, md[0], md[1], md[2], md[3], s, a, b, f.m, f.n,
                                p.f_off});
+          if (pk.scales) pk.scales->push_back(p.scale);
           add_seg(pk, out_row, f.m, {p});
         }
     }
@@ -92,7 +93,8 @@ void pack_group(PackSink &pk, const Tree &t, const std::vector<const Butterfly *
     const int64_t m = hi - lo;
     std::vector<Pair> prs;
     if (forward) {
-      Pair p;
+      Pair p{};
+      p.scale = 1.0f;
       p.f_off = pk.reserve_dev(m, m);
       p.in_buf = 0;
       p.in_row = lo;
@@ -101,6 +103,7 @@ void pack_group(PackSink &pk, const Tree &t, const std::vector<const Butterfly *
       pk.jobs->push_back({p.f_off, lo, int32_t(m), int32_t(pk.jobcols->size()), int32_t(m)});
       for (int32_t c = lo; c < hi; ++c) pk.jobcols->push_back(c);
       pk.table->push_back({0, LH, g, 0, 0, 0, 0, 0, m, m, p.f_off});
+      if (pk.scales) pk.scales->push_back(1.0f);
       prs.push_back(p);
     }
     for (auto [k, a] : cover[size_t(g)]) {
@@ -110,7 +113,8 @@ void pack_group(PackSink &pk, const Tree &t, const std::vector<const Butterfly *
       if (r == 0) continue;
       int64_t md[4];
       meta(bf, md);
-      Pair p;
+      Pair p{};
+      p.scale = 1.0f;
       p.in_buf = 1;
       p.in_row = int32_t(off[size_t(k)][bf.L][size_t(a)]);
       p.n = int32_t(r);
@@ -121,9 +125,10 @@ void pack_group(PackSink &pk, const Tree &t, const std::vector<const Butterfly *
         pk.jobs->push_back({p.f_off, lo, int32_t(m), int32_t(pk.jobcols->size()), int32_t(r)});
         pk.jobcols->insert(pk.jobcols->end(), sk.begin(), sk.end());
       } else {
-        p.f_off = pk.put_host(bf.B[size_t(a)]);
+        p.f_off = pk.put_host(bf.B[size_t(a)], &p.scale);
       }
       pk.table->push_back({3, md[0], md[1], md[2], md[3], bf.L, a, 0, m, r, p.f_off});
+      if (pk.scales) pk.scales->push_back(p.scale);
       prs.push_back(p);
     }
     if (!prs.empty()) add_seg(pk, lo, m, prs);

@@ -14,7 +14,9 @@ struct PackSink {
   std::vector<Launch> launches;
   int64_t t_rows = 0;
   std::vector<BlockRec> *table = nullptr;
-  std::function<int64_t(const Mat &)> put_host;          // host-valued block -> arena offset
+  // host-valued block -> arena offset; sets the block's load scale
+  std::function<int64_t(const Mat &, float *)> put_host;
+  std::vector<float> *scales = nullptr;                   // per table row, if wanted
   std::function<int64_t(int64_t, int64_t)> reserve_dev;  // device-generated block -> offset
   std::vector<EntryJob> *jobs = nullptr;
   std::vector<int32_t> *jobcols = nullptr;

@@ -208,7 +208,7 @@ void validate_params(const hodbf_build_params &p) {
   if (p.precond_prec != HODBF_P_NONE && !(p.tol_fact > 0 && p.tol_fact < 1))
     fail(HODBF_E_ARG, "tol_fact must lie in (0, 1)");
   if (p.leaf_size < 1 || p.leaf_size > 64) fail(HODBF_E_ARG, "leaf_size must be 1..64");
-  if (p.precond_prec < HODBF_P_NONE || p.precond_prec > HODBF_P_BOTH)
+  if (p.precond_prec < 0 || p.precond_prec > 7)
     fail(HODBF_E_ARG, "unknown precond_prec");
   if (p.precond_min_level < 0) fail(HODBF_E_ARG, "precond_min_level must be >= 0");
   if (!p.eps_r) fail(HODBF_E_ARG, "eps_r is NULL");

@@ -77,7 +77,33 @@ struct DenseSource final : EntrySource {
   }
 };
 
-__attribute__((unused)) uint32_t to_bf16_pair(cd v) {
+// IEEE binary16 with round to nearest even (inputs are pre-scaled to |v| <= 1).
+uint32_t f32_to_f16(float f) {
+  uint32_t x;
+  std::memcpy(&x, &f, 4);
+  const uint32_t sign = (x >> 16) & 0x8000u;
+  int32_t e = int32_t((x >> 23) & 0xFF) - 127 + 15;
+  uint32_t mant = x & 0x7FFFFFu;
+  if (((x >> 23) & 0xFF) == 0xFF) return sign | 0x7C00u | (mant ? 0x200u : 0u);
+  if (e >= 31) return sign | 0x7C00u;
+  if (e <= 0) {  // subnormal half or zero
+    if (e < -10) return sign;
+    mant |= 0x800000u;
+    const int shift = 14 - e;
+    uint32_t h = mant >> shift;
+    const uint32_t rem = mant & ((1u << shift) - 1), half = 1u << (shift - 1);
+    if (rem > half || (rem == half && (h & 1u))) ++h;
+    return sign | h;
+  }
+  uint32_t h = (uint32_t(e) << 10) | (mant >> 13);
+  const uint32_t rem = mant & 0x1FFFu;
+  if (rem > 0x1000u || (rem == 0x1000u && (h & 1u))) ++h;  // may carry into the exponent
+  return sign | h;
+}
+
+uint32_t to_f16_pair(cd v) { return f32_to_f16(float(v.real())) | (f32_to_f16(float(v.imag())) << 16); }
+
+uint32_t to_bf16_pair(cd v) {
   auto cv = [](float f) -> uint32_t {
     uint32_t u;
     std::memcpy(&u, &f, 4);
@@ -152,13 +178,22 @@ void build_precond(hodbf_op &op, hipStream_t st) {
   const int LH = t.depth;
   const auto &p = op.params;
   pd.min_level = std::min(p.precond_min_level, LH);
-  const bool want32 = p.precond_prec == HODBF_P_FP32 || p.precond_prec == HODBF_P_BOTH;
-  const bool want16 = p.precond_prec == HODBF_P_BF16 || p.precond_prec == HODBF_P_BOTH;
-  std::vector<cd> host;  // all factor values, packed; converted at upload
-  auto put = [&](const Mat &f) -> int64_t {
+  const bool want32 = (p.precond_prec & HODBF_P_FP32) != 0;
+  const bool wantb16 = (p.precond_prec & HODBF_P_BF16) != 0;
+  const bool wanth16 = (p.precond_prec & HODBF_P_FP16) != 0;
+  // all factor values, each block divided by its largest component magnitude (the
+  // pair's load scale), so that the FP16 copy neither overflows nor underflows
+  std::vector<cd> host;
+  pd.scales.clear();
+  auto put = [&](const Mat &f, float *scale) -> int64_t {
     const int64_t off = (int64_t(host.size()) + 15) & ~int64_t(15);
     host.resize(size_t(off + int64_t(f.m) * f.n));
-    std::copy(f.v.begin(), f.v.end(), host.begin() + off);
+    double mx = 0;
+    for (const cd &v : f.v) mx = std::max({mx, std::abs(v.real()), std::abs(v.imag())});
+    const float s = mx > 0 ? float(mx) : 1.0f;
+    const double inv = 1.0 / double(s);
+    for (size_t e = 0; e < f.v.size(); ++e) host[size_t(off) + e] = f.v[e] * inv;
+    *scale = s;
     return off;
   };
   // leaves: dense inverses (FP64 on the host, 64 x 64)
@@ -175,13 +210,14 @@ void build_precond(hodbf_op &op, hipStream_t st) {
       for (int c = 0; c < m; ++c)
         for (int r = 0; r < m; ++r) D.v[size_t(c) * m + r] = op.ker.entry(lo + r, lo + c);
       small_inverse(D.v, m);
-      Pair pr;
-      pr.f_off = put(D);
+      Pair pr{};
+      pr.f_off = put(D, &pr.scale);
       pr.in_row = lo;
       pr.n = m;
       pr.lda = m;
       pr.in_buf = 0;
       pk.table->push_back({0, LH, g, 0, 0, 0, 0, 0, m, m, pr.f_off});
+      pd.scales.push_back(pr.scale);
       Seg s{lo, m, int32_t(pk.pairs.size()), int32_t(pk.pairs.size() + 1)};
       pk.pairs.push_back(pr);
       pk.segs.push_back(s);
@@ -248,6 +284,7 @@ void build_precond(hodbf_op &op, hipStream_t st) {
     }
     PackSink pk;
     pk.table = &pd.table;
+    pk.scales = &pd.scales;
     pk.put_host = put;
     std::vector<const Butterfly *> ptrs;
     for (auto &bf : bfs) ptrs.push_back(&bf);
@@ -271,18 +308,23 @@ void build_precond(hodbf_op &op, hipStream_t st) {
     for (size_t i = 0; i < count; ++i) f[i] = make_float2(float(host[i].real()), float(host[i].imag()));
     pd.F32.upload(f.data(), count * sizeof(float2), st);
   }
-  if (want16) {
+  if (wantb16) {
     std::vector<uint32_t> f(count);
     for (size_t i = 0; i < count; ++i) f[i] = to_bf16_pair(host[i]);
     pd.BF16.upload(f.data(), count * sizeof(uint32_t), st);
   }
-  const size_t total = op.fwdF.bytes + pd.F32.bytes + pd.BF16.bytes;
+  if (wanth16) {
+    std::vector<uint32_t> f(count);
+    for (size_t i = 0; i < count; ++i) f[i] = to_f16_pair(host[i]);
+    pd.F16.upload(f.data(), count * sizeof(uint32_t), st);
+  }
+  const size_t total = op.fwdF.bytes + pd.F32.bytes + pd.BF16.bytes + pd.F16.bytes;
   if (p.hbm_budget && total > p.hbm_budget) fail(HODBF_E_NOMEM, "operator exceeds hbm_budget");
   int64_t ent = 0;
   for (auto &r : pd.table) ent += r.m * r.n;
   pd.entries = ent;
   pd.max_rank = maxr;
-  pd.default_ft = want16 ? FT_BF16 : FT_C64;
+  pd.default_ft = wanth16 ? FT_F16 : (want32 ? FT_C64 : FT_BF16);
   pd.present = true;
   op.id_count += ids;
   pd.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

@@ -12,7 +12,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import C64, C128, P_BF16, P_BOTH, P_FP32, P_NONE, check, lib
+from ._lib import C64, C128, P_BF16, P_BOTH, P_FP16, P_FP32, P_NONE, check, lib
 
 
 def _stream():
@@ -76,7 +76,7 @@ class Operator:
     def apply_tree(self, x: torch.Tensor, which: int = 0) -> torch.Tensor:
         """Products on internal-layout vectors: x of shape (N, R) complex64 in tree order
         (row t = user index perm[t]), contiguous, so element (t, q) sits at t*R + q.
-        which: 0 Z_con, 1 P (default copy), 2 P FP32 copy, 3 P BF16 copy."""
+        which: 0 Z_con, 1 P (default copy), 2 P FP32 copy, 3 P BF16 copy, 4 P FP16 copy."""
         if x.dtype != torch.complex64 or not x.is_contiguous() or x.dim() != 2:
             raise ValueError("x must be a contiguous (N, R) complex64 tensor")
         y = torch.empty_like(x)
@@ -95,13 +95,13 @@ class Operator:
     def solve(self, b: torch.Tensor, tol=1e-4, restart=20, max_iter=3000, use_precond=1):
         """x ~ Z^{-1} b by right-preconditioned FGMRES; returns (x, info dict).
 
-        use_precond: 0 none, 1 the operator's default copy, 'fp32' or 'bf16'.
+        use_precond: 0 none, 1 the operator's default copy, 'fp32', 'bf16' or 'fp16'.
         """
         if b.dtype != torch.complex128:
             raise ValueError("b must be complex128")
         bc, R = _as_cols(b, self.n)
         x = torch.empty_like(bc)
-        up = {"fp32": 8 + P_FP32, "bf16": 8 + P_BF16}.get(use_precond, use_precond)
+        up = {"fp32": 8 + P_FP32, "bf16": 8 + P_BF16, "fp16": 8 + P_FP16}.get(use_precond, use_precond)
         opts = _lib.SolveOpts(tol=tol, restart=restart, max_iter=max_iter, use_precond=int(up))
         iters = np.zeros(R, dtype=np.int32)
         conv = np.zeros(R, dtype=np.int32)
@@ -137,9 +137,9 @@ class Operator:
         """(table as int64 (k, 11), values complex64) of the forward operator."""
         return self.export(1, np.int64).reshape(-1, 11), self.export(2, np.complex64)
 
-    def precond_blocks(self, copy="default"):
-        vals = self.export(5 if copy == "bf16" else 4, np.complex64)
+    def precond_blocks(self, copy="fp32"):
+        vals = self.export({"fp32": 4, "bf16": 5, "fp16": 6}[copy], np.complex64)
         return self.export(3, np.int64).reshape(-1, 11), vals
 
 
-__all__ = ["Operator", "P_NONE", "P_FP32", "P_BF16", "P_BOTH"]
+__all__ = ["Operator", "P_NONE", "P_FP32", "P_BF16", "P_BOTH", "P_FP16"]
