@@ -151,94 +151,181 @@ __global__ __launch_bounds__(256) void k_grouped_gemv(const Seg *__restrict__ se
   }
 }
 
-// MFMA grouped GEMM, complex FP32 factors.  The complex product is one real GEMM:
-// a factor row (ar_0, ai_0, ar_1, ai_1, ...) times Xt, where Xt row 2c holds
-// (xr, xi) and row 2c+1 holds (-xi, xr) for every right-hand side, so output column
-// pair (2q, 2q+1) is (Re y_q, Im y_q).  v_mfma_f32_16x16x4f32: lane l holds
-// A[l % 16][l / 16], B[l / 16][l % 16], and D[4 (l / 16) + v][l % 16].  Four
-// MFMAs consume 8 complex columns: slot kk of MFMA t is real column 4 kk + t, i.e.
-// complex column 2 kk + t / 2, part t % 2.  Each workgroup owns one segment (<= 64
-// rows = 4 row tiles); its waves split row tiles and 8-RHS column tiles.
-template <typename FT>
-__global__ __launch_bounds__(256) void k_grouped_mfma_f32(const Seg *__restrict__ segs,
-                                                          const Pair *__restrict__ pairs,
-                                                          const FT *__restrict__ F,
-                                                          const float2 *__restrict__ X,
-                                                          const float2 *__restrict__ T,
-                                                          float2 *__restrict__ OUT, int R,
-                                                          int beta) {
-  const Seg sg = segs[blockIdx.x];
+// MFMA grouped GEMM with FP32 arithmetic (complex FP32 or FP16-stored factors).
+// The complex product is one real GEMM: a factor row (ar_0, ai_0, ar_1, ai_1, ...)
+// times Xt, where Xt row 2c holds (xr, xi) and row 2c+1 holds (-xi, xr) for every
+// right-hand side, so output column pair (2q, 2q+1) is (Re y_q, Im y_q).
+// v_mfma_f32_16x16x4f32: lane l holds A[l % 16][l / 16], B[l / 16][l % 16] and
+// D[4 (l / 16) + v][l % 16].  Four MFMAs consume 8 complex columns: slot kk of MFMA t
+// is real column 4 kk + t, i.e. complex column 2 kk + t / 2, part t % 2.
+// One workgroup owns one segment (<= 64 output rows).  Its output tiles (16 rows x 8
+// right-hand sides) are dealt to the four waves as a cw x rw grid: wave w takes the
+// column tiles congruent to w % cw and the row tiles congruent to w / cw, so every
+// row count keeps all waves busy and a wave reuses its input fragments across its row
+// tiles.  Factor columns and input rows are streamed in chunks of KC = 16 complex
+// columns: each chunk is loaded once per workgroup, coalesced, into LDS; the next
+// chunk is fetched into registers while the current one is multiplied.  The chunk
+// loop is instantiated per (row tiles, column tiles) of a wave so that its inner
+// loops have fixed trip counts; every instantiation runs the same barriers.
+constexpr int kKC = 16;  // complex K rows per chunk
+constexpr int kXS = 68;  // LDS stride of an input row (64 + 4 complex: conflict-free reads)
+constexpr int kAS = 72;  // LDS stride of a factor column (64 + 8 complex: conflict-free)
+
+template <typename FT, int NRI, int NCI>
+__device__ __forceinline__ void grouped_chunks(const Seg sg, const Pair *__restrict__ pairs,
+                                               const FT *__restrict__ F,
+                                               const float2 *__restrict__ X,
+                                               const float2 *__restrict__ T,
+                                               float2 *__restrict__ OUT, int R, int beta,
+                                               int q0, int Rc, int wr, int rw, int wc, int cw,
+                                               float2 *xs, float2 *as) {
   const int m = sg.m;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nrt = (m + 15) >> 4;
-  const int nrtp = nrt == 3 ? 4 : nrt;
-  const int wpr = 4 / nrtp;
-  const int rt = wave / wpr;
-  if (rt >= nrt) return;
-  const int sub = wave % wpr;
-  const int ia = rt * 16 + (lane & 15);  // A row of this lane
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int i16 = lane & 15;
   const int kk = lane >> 4;
-  const int jc = lane & 15;
-  const int qo = jc >> 1, op = jc & 1;
-  for (int q0 = 0; q0 < R; q0 += 64) {
-    const int Rc = R - q0 < 64 ? R - q0 : 64;
-    const int nnt = (Rc + 7) >> 3;
-    floatx4 acc[8];
+  const int qo = i16 >> 1, op = i16 & 1;
+  const float2 z2 = make_float2(0.f, 0.f);
+  floatx4 acc[NRI > 0 ? NRI * NCI : 1];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    for (int p = sg.p0; p < sg.p1; ++p) {
-      const Pair pr = pairs[p];
-      const FT *A = F + pr.f_off;
-      const float2 *in = (pr.in_buf ? T : X) + int64_t(pr.in_row) * R;
-      const int n = pr.n;
-      const float sc = pr.scale;
-      for (int c0 = 0; c0 < n; c0 += 8) {
-        const int c = c0 + 2 * kk;
-        const bool rok = ia < m;
-        const float2 z2 = make_float2(0.f, 0.f);
-        float2 a0 = (rok && c < n) ? load_factor(A, int64_t(c) * pr.lda + ia) : z2;
-        float2 a1 = (rok && c + 1 < n) ? load_factor(A, int64_t(c + 1) * pr.lda + ia) : z2;
-        a0.x *= sc;
-        a0.y *= sc;
-        a1.x *= sc;
-        a1.y *= sc;
+  for (int j = 0; j < (NRI > 0 ? NRI * NCI : 1); ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  float2 xr[4], ar[4];
+  int p = sg.p0, k0 = 0;
+  Pair pr = pairs[p];
+#define HODBF_LOAD_CHUNK(PP, KB)                                                              \
+  {                                                                                           \
+    const float2 *xb_ = ((PP).in_buf ? T : X) + int64_t((PP).in_row + (KB)) * R + q0;         \
+    const FT *A_ = F + (PP).f_off;                                                            \
+    _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                           \
+      const int e = tid + 256 * i;                                                            \
+      const int hi = e >> 6, lo = e & 63; /* x: row hi, column lo; A: column hi, row lo */    \
+      const bool kin = (KB) + hi < (PP).n;                                                    \
+      xr[i] = (kin && lo < Rc) ? xb_[int64_t(hi) * R + lo] : z2;                             \
+      float2 a_ = (kin && lo < m) ? load_factor(A_, int64_t((KB) + hi) * (PP).lda + lo) : z2; \
+      a_.x *= (PP).scale;                                                                     \
+      a_.y *= (PP).scale;                                                                     \
+      ar[i] = a_;                                                                             \
+    }                                                                                         \
+  }
+  HODBF_LOAD_CHUNK(pr, k0);
+  while (true) {
+    __syncthreads();  // previous chunk fully consumed
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const int nt = sub + j * wpr;
-          if (nt < nnt) {
-            const int q = q0 + nt * 8 + qo;
-            const bool qok = q < R;
-            const float2 x0 = (qok && c < n) ? in[int64_t(c) * R + q] : z2;
-            const float2 x1 = (qok && c + 1 < n) ? in[int64_t(c + 1) * R + q] : z2;
-            const float b0 = op ? x0.y : x0.x;
-            const float b1 = op ? x0.x : -x0.y;
-            const float b2 = op ? x1.y : x1.x;
-            const float b3 = op ? x1.x : -x1.y;
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.x, b0, acc[j], 0, 0, 0);
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.y, b1, acc[j], 0, 0, 0);
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.x, b2, acc[j], 0, 0, 0);
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.y, b3, acc[j], 0, 0, 0);
-          }
-        }
-      }
+    for (int i = 0; i < 4; ++i) {
+      const int e = tid + 256 * i;
+      xs[(e >> 6) * kXS + (e & 63)] = xr[i];
+      as[(e >> 6) * kAS + (e & 63)] = ar[i];
     }
+    __syncthreads();
+    int pn = p, kn = k0 + kKC;
+    Pair prn = pr;
+    if (kn >= pr.n) {
+      pn = p + 1;
+      kn = 0;
+      if (pn < sg.p1) prn = pairs[pn];
+    }
+    const bool has_next = pn < sg.p1;
+    if (has_next) HODBF_LOAD_CHUNK(prn, kn);  // in flight during the products below
+    if (NRI > 0) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int nt = sub + j * wpr;
-      if (nt < nnt) {
-        const int q = q0 + nt * 8 + qo;
-        if (q < R) {
+      for (int h = 0; h < 2; ++h) {
+        const int c0 = 8 * h + 2 * kk;  // this lane's two complex K rows of the half chunk
+        float2 x0[NCI], x1[NCI], a0[NRI > 0 ? NRI : 1], a1[NRI > 0 ? NRI : 1];
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int row = rt * 16 + 4 * kk + v;
-            if (row < m) {
-              float *o = reinterpret_cast<float *>(OUT + int64_t(sg.out_row + row) * R + q) + op;
-              *o = beta ? *o + acc[j][v] : acc[j][v];
+        for (int ci = 0; ci < NCI; ++ci) {
+          const int col = (wc + ci * cw) * 8 + qo;
+          x0[ci] = xs[c0 * kXS + col];
+          x1[ci] = xs[(c0 + 1) * kXS + col];
+        }
+#pragma unroll
+        for (int ri = 0; ri < NRI; ++ri) {
+          const int rt = wr + ri * rw;
+          a0[ri] = as[c0 * kAS + rt * 16 + i16];
+          a1[ri] = as[(c0 + 1) * kAS + rt * 16 + i16];
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+#pragma unroll
+          for (int ri = 0; ri < NRI; ++ri) {
+            const float2 a = t < 2 ? a0[ri] : a1[ri];
+            const float av = (t & 1) ? a.y : a.x;
+#pragma unroll
+            for (int ci = 0; ci < NCI; ++ci) {
+              const float2 x = t < 2 ? x0[ci] : x1[ci];
+              const float bv = (t & 1) ? (op ? x.x : -x.y) : (op ? x.y : x.x);
+              acc[ri * NCI + ci] =
+                  __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[ri * NCI + ci], 0, 0, 0);
             }
           }
         }
       }
     }
+    if (!has_next) break;
+    p = pn;
+    k0 = kn;
+    pr = prn;
+  }
+#undef HODBF_LOAD_CHUNK
+#pragma unroll
+  for (int ri = 0; ri < NRI; ++ri) {
+    const int rt = wr + ri * rw;
+#pragma unroll
+    for (int ci = 0; ci < NCI; ++ci) {
+      const int q = q0 + (wc + ci * cw) * 8 + qo;
+      if (q < R) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = rt * 16 + 4 * kk + v;
+          if (row < m) {
+            float *o = reinterpret_cast<float *>(OUT + int64_t(sg.out_row + row) * R + q) + op;
+            *o = beta ? *o + acc[ri * NCI + ci][v] : acc[ri * NCI + ci][v];
+          }
+        }
+      }
+    }
+  }
+}
+
+template <typename FT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_grouped_mfma_f32(const Seg *__restrict__ segs,
+                                                          const Pair *__restrict__ pairs,
+                                                          const FT *__restrict__ F,
+                                                          const float2 *__restrict__ X,
+                                                          const float2 *__restrict__ T,
+                                                          float2 *__restrict__ OUT, int R,
+                                                          int beta, int RQ) {
+  __shared__ float2 xs[kKC * kXS];
+  __shared__ float2 as[kKC * kAS];
+  const Seg sg = segs[blockIdx.x];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nrt = (sg.m + 15) >> 4;
+  // blockIdx.y selects a slice of RQ (<= 64) right-hand sides; launches with few
+  // segments use narrow slices to put more workgroups on the chip
+  const int qend = min(R, int(blockIdx.y + 1) * RQ);
+  for (int q0 = blockIdx.y * RQ; q0 < qend; q0 += 64) {
+    const int Rc = qend - q0 < 64 ? qend - q0 : 64;
+    const int nnt = (Rc + 7) >> 3;
+    const int cw = nnt >= 4 ? 4 : (nnt >= 2 ? 2 : 1);  // wave columns
+    const int rw = 4 / cw;                             // wave rows
+    const int wc = wave % cw, wr = wave / cw;
+    // row tiles wr, wr + rw, ... below nrt; column tiles wc, wc + cw below nnt (<= 2)
+    const int nri = wr < nrt ? (nrt - wr + rw - 1) / rw : 0;
+    const int nci = wc < nnt ? (wc + cw < nnt ? 2 : 1) : 0;
+    const int sel = nci == 0 ? 0 : nri * 2 + (nci - 1);  // wave-uniform
+#define HODBF_CHUNKS(NR, NC)                                                                  \
+  grouped_chunks<FT, NR, NC>(sg, pairs, F, X, T, OUT, R, beta, q0, Rc, wr, rw, wc, cw, xs, as)
+    switch (sel) {
+      case 2: HODBF_CHUNKS(1, 1); break;
+      case 3: HODBF_CHUNKS(1, 2); break;
+      case 4: HODBF_CHUNKS(2, 1); break;
+      case 5: HODBF_CHUNKS(2, 2); break;
+      case 6: HODBF_CHUNKS(3, 1); break;
+      case 7: HODBF_CHUNKS(3, 2); break;
+      case 8: HODBF_CHUNKS(4, 1); break;
+      case 9: HODBF_CHUNKS(4, 2); break;
+      default: HODBF_CHUNKS(0, 1); break;  // no tiles: loads and barriers only
+    }
+#undef HODBF_CHUNKS
+    __syncthreads();  // the next right-hand-side chunk reuses the LDS buffers
   }
 }
 
@@ -355,12 +442,18 @@ void launch_grouped(const Seg *segs, const Pair *pairs, int64_t s0, int64_t ns, 
                          pairs, static_cast<const FF16 *>(F), X, T, OUT, R, beta, ns);
     return;
   }
+  // right-hand-side slice per workgroup: 64, or narrower when a launch has too few
+  // segments to give every SIMD several waves
+  int RQ = 64;
+  while (RQ > 16 && ns * ((R + RQ - 1) / RQ) < 2048) RQ >>= 1;
+  if (RQ > R) RQ = R;
+  const dim3 grid(unsigned(ns), unsigned((R + RQ - 1) / RQ));
   if (ftype == FT_C64)
-    hipLaunchKernelGGL(k_grouped_mfma_f32<float2>, dim3(unsigned(ns)), dim3(256), 0, st, sp, pairs,
-                       static_cast<const float2 *>(F), X, T, OUT, R, beta);
+    hipLaunchKernelGGL(k_grouped_mfma_f32<float2>, grid, dim3(256), 0, st, sp, pairs,
+                       static_cast<const float2 *>(F), X, T, OUT, R, beta, RQ);
   else if (ftype == FT_F16)
-    hipLaunchKernelGGL(k_grouped_mfma_f32<FF16>, dim3(unsigned(ns)), dim3(256), 0, st, sp, pairs,
-                       static_cast<const FF16 *>(F), X, T, OUT, R, beta);
+    hipLaunchKernelGGL(k_grouped_mfma_f32<FF16>, grid, dim3(256), 0, st, sp, pairs,
+                       static_cast<const FF16 *>(F), X, T, OUT, R, beta, RQ);
   else
     hipLaunchKernelGGL(k_grouped_mfma_bf16, dim3(unsigned(ns)), dim3(256), 0, st, sp, pairs,
                        static_cast<const uint32_t *>(F), X, T, OUT, R, beta);
