@@ -271,7 +271,7 @@ __device__ __forceinline__ void grouped_chunks(const Seg sg, const Pair *__restr
 #pragma unroll
     for (int ci = 0; ci < NCI; ++ci) {
       const int q = q0 + (wc + ci * cw) * 8 + qo;
-      if (q < R) {
+      if (q < q0 + Rc) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int row = rt * 16 + 4 * kk + v;
