@@ -133,23 +133,29 @@ def small_case(seed: int, sides=(12, 10, 9), h: float = 1.0 / 10, eps_range=(1.0
     return dict(grid=make_grid(nx, ny, nz, h, eps), dirs=dirs, x=x, nrhs=nrhs)
 
 
-def serving_requests(seed: int = 4, count: int = 200, rate: float = 1.0) -> list:
-    """Poisson stream of solve requests over the three cube sizes of the serving workload.
+def serving_requests(seed: int = 4, count: int = 200, rate: float = 1.0, sizes=None,
+                     scatterers_per_size: int = 3) -> list:
+    """Poisson stream of solve requests over cube sizes (default: 16^3 in 1 wavelength,
+    32^3 in 4, 64^3 in 8).
 
-    Each request: arrival time (exponential gaps at ``rate`` per second), grid size
-    (16^3 in 1 wavelength, 32^3 in 4, 64^3 in 8), per-voxel eps_r ~ U[1, 12] drawn by
-    the request's own seed, and a right-hand-side count ~ U{1..16}.
+    Each request: arrival time (exponential gaps at ``rate`` per second), a size, a
+    scatterer drawn from a pool of ``scatterers_per_size`` seeded permittivity fields of
+    that size (eps_r ~ U[1, 12] per voxel, so operators can stay resident across
+    requests), and a right-hand-side count ~ U{1..16}.
     """
     rng = np.random.default_rng(seed)
-    sizes = [((16, 16, 16), 1.0), ((32, 32, 32), 4.0), ((64, 64, 64), 8.0)]
+    if sizes is None:
+        sizes = [((16, 16, 16), 1.0), ((32, 32, 32), 4.0), ((64, 64, 64), 8.0)]
+    pool = rng.integers(0, 2**31 - 1, size=(len(sizes), scatterers_per_size))
     t = 0.0
     out = []
     for i in range(count):
         t += rng.exponential(1.0 / rate)
-        which = int(rng.integers(0, 3))
+        which = int(rng.integers(0, len(sizes)))
         nrhs = int(rng.integers(1, 17))
+        k = int(rng.integers(0, scatterers_per_size))
         out.append(dict(id=i, arrival=t, sides=sizes[which][0], box=sizes[which][1],
-                        nrhs=nrhs, eps_seed=int(rng.integers(0, 2**31 - 1))))
+                        nrhs=nrhs, eps_seed=int(pool[which, k]), dir_seed=int(rng.integers(0, 2**31 - 1))))
     return out
 
 
@@ -158,5 +164,5 @@ def request_inputs(req: dict) -> dict:
     nx, ny, nz = req["sides"]
     rng = np.random.default_rng(req["eps_seed"])
     eps = rng.uniform(1.0, 12.0, size=(nz, ny, nx)).reshape(-1).astype(np.complex128)
-    dirs = random_directions(rng, req["nrhs"])
+    dirs = random_directions(np.random.default_rng(req["dir_seed"]), req["nrhs"])
     return dict(grid=make_grid(nx, ny, nz, req["box"] / nx, eps), dirs=dirs)

@@ -1,0 +1,44 @@
+"""The serving loop on the GPU: every request's result is the same alone and in the mix
+(within the solve tolerance), operators stay resident and pending requests batch."""
+import numpy as np
+import pytest
+
+from oracle import vie
+from synth.workloads import random_directions, small_case
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def test_alone_equals_in_mix():
+    from paper_2111_01730_amd import serving
+    from paper_2111_01730_amd.hodbf import P_FP32, Operator
+    cases = [small_case(71, sides=(8, 8, 8), eps_range=(1.0, 12.0)),
+             small_case(72, sides=(8, 8, 8), eps_range=(1.0, 12.0)),
+             small_case(73, sides=(10, 9, 8), eps_range=(1.0, 12.0))]
+    rng = np.random.default_rng(5)
+    reqs = []
+    for i in range(9):
+        c = cases[i % 3]
+        reqs.append(serving.Request(id=i, grid=c["grid"], dirs=random_directions(rng, 1 + i % 4),
+                                    tol=1e-6))
+    kw = dict(tol_con=1e-5, tol_fact=1e-4, precond=P_FP32)
+    srv = serving.Server(hbm_budget=8 << 30, slots=2, max_rhs=16, **kw)
+    print("[serving mix of 9 requests over 3 scatterers]", flush=True)
+    res = serving.replay(srv, reqs)
+    srv.close()
+    assert all(r.converged for r in res)
+    assert max(r.batch_size for r in res) >= 2  # some requests shared a solve
+    for r, q in zip(res, reqs):
+        op = Operator(q.grid, **kw)
+        b = op.plane_wave(q.dirs)
+        x, info = op.solve(b, tol=1e-6)
+        xa = x.cpu().numpy()
+        d = np.linalg.norm(r.x - xa, axis=0) / np.linalg.norm(xa, axis=0)
+        assert np.all(d <= 1e-4), (q.id, d)
+        # and the mixed result solves the exact system to the tolerance (+ compression)
+        Z = vie.dense(q.grid)
+        bn = b.cpu().numpy()
+        rel = np.linalg.norm(Z @ r.x - bn, axis=0) / np.linalg.norm(bn, axis=0)
+        assert np.all(rel <= 1e-6 + 1e-4)
+        op.close()
