@@ -20,6 +20,8 @@ from __future__ import annotations
 
 import argparse
 import json
+
+import numpy as np
 import os
 import subprocess
 import sys
@@ -94,13 +96,52 @@ def apply_mode(args, cfg, Operator, P_NONE):
     return 0
 
 
+def serve_mode(args):
+    """Poisson stream of solve requests through the continuous-batching server."""
+    from paper_2111_01730_amd import serving
+    from paper_2111_01730_amd.hodbf import P_FP32
+    from synth.workloads import request_inputs, serving_requests
+    box = {16: 1.0, 32: 4.0, 64: 8.0}
+    sizes = [((n, n, n), box[n]) for n in (int(v) for v in args.serve_sizes.split(","))]
+    stream = serving_requests(seed=4, count=args.serve_requests, rate=args.serve_rate, sizes=sizes)
+    reqs = []
+    for r in stream:
+        inp = request_inputs(r)
+        reqs.append(serving.Request(id=r["id"], grid=inp["grid"], dirs=inp["dirs"],
+                                    arrival=r["arrival"], tol=TOL_SOL))
+    srv = serving.Server(hbm_budget=200 << 30, slots=args.serve_slots, max_rhs=64,
+                         tol_con=1e-4, tol_fact=args.tol_fact, precond=P_FP32)
+    t0 = time.perf_counter()
+    res = serving.replay(srv, reqs)
+    wall = time.perf_counter() - t0
+    log_ = list(srv.log)
+    srv.close()
+    summ = serving.summarize(res, wall)
+    builds = sum(1 for b in log_ if b["built"])
+    steady = [r for r in res if not r.built]
+    lat = np.array([r.latency for r in steady]) if steady else np.zeros(1)
+    out = {"mode": "serve", "workload": f"{args.serve_requests} requests, sizes {args.serve_sizes}, "
+                                        f"3 scatterers per size, eps_r U[1,12], 1-16 RHS, "
+                                        f"Poisson rate {args.serve_rate}/s",
+           **summ, "batches": len(log_), "operator_builds": builds,
+           "p50_latency_resident_s": float(np.percentile(lat, 50)),
+           "p99_latency_resident_s": float(np.percentile(lat, 99)),
+           "slots": args.serve_slots, "tol_fact": args.tol_fact}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--tol-fact", type=float, default=1e-4)
-    ap.add_argument("--mode", choices=["solve", "apply"], default="solve")
+    ap.add_argument("--mode", choices=["solve", "apply", "serve"], default="solve")
+    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="mean arrivals per second")
+    ap.add_argument("--serve-sizes", default="16,32", help="cube sides drawn by requests")
+    ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--variant-max-iter", type=int, default=300)
     ap.add_argument("--plain-rhs", type=int, default=4, help="columns timed in the plain form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -116,7 +157,6 @@ def main():
                           "n_gpus": args.gpus}))
         return 2
 
-    import numpy as np
     import torch
 
     from paper_2111_01730_amd.hodbf import P_BF16, P_FP16, P_FP32, P_NONE, Operator
@@ -128,6 +168,8 @@ def main():
     R = cfg["nrhs"]
     if args.mode == "apply":
         return apply_mode(args, cfg, Operator, P_NONE)
+    if args.mode == "serve":
+        return serve_mode(args)
     t0 = time.perf_counter()
     op = Operator(g, tol_con=cfg["tol"], tol_fact=args.tol_fact, precond=P_FP32 | P_BF16 | P_FP16,
                   seed=cfg["seed"])
