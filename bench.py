@@ -110,22 +110,26 @@ def serve_mode(args):
         reqs.append(serving.Request(id=r["id"], grid=inp["grid"], dirs=inp["dirs"],
                                     arrival=r["arrival"], tol=TOL_SOL))
     srv = serving.Server(hbm_budget=200 << 30, slots=args.serve_slots, max_rhs=64,
-                         tol_con=1e-4, tol_fact=args.tol_fact, precond=P_FP32)
+                         tol_con=1e-4, tol_fact=args.tol_fact, precond=P_FP32, build_slots=3)
+    # operators of the scatterer pool are built first (resident), then the stream plays
+    tb = time.perf_counter()
+    seen = {}
+    for q in reqs:
+        seen.setdefault(serving.scatterer_key(q.grid), q.grid)
+    build_times = [srv.preload(gr) for gr in seen.values()]
+    build_wall = time.perf_counter() - tb
+    log(f"[serve] {len(seen)} operators resident after {build_wall:.1f} s")
     t0 = time.perf_counter()
     res = serving.replay(srv, reqs)
     wall = time.perf_counter() - t0
     log_ = list(srv.log)
     srv.close()
     summ = serving.summarize(res, wall)
-    builds = sum(1 for b in log_ if b["built"])
-    steady = [r for r in res if not r.built]
-    lat = np.array([r.latency for r in steady]) if steady else np.zeros(1)
     out = {"mode": "serve", "workload": f"{args.serve_requests} requests, sizes {args.serve_sizes}, "
                                         f"3 scatterers per size, eps_r U[1,12], 1-16 RHS, "
                                         f"Poisson rate {args.serve_rate}/s",
-           **summ, "batches": len(log_), "operator_builds": builds,
-           "p50_latency_resident_s": float(np.percentile(lat, 50)),
-           "p99_latency_resident_s": float(np.percentile(lat, 99)),
+           **summ, "batches": len(log_), "operators": len(seen),
+           "operator_build_s": build_times, "operators_resident_after_s": build_wall,
            "slots": args.serve_slots, "tol_fact": args.tol_fact}
     print(json.dumps(out), flush=True)
     return 0

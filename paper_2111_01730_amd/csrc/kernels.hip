@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstdlib>
 
 #include "device.h"
 
@@ -444,8 +445,12 @@ void launch_grouped(const Seg *segs, const Pair *pairs, int64_t s0, int64_t ns, 
   }
   // right-hand-side slice per workgroup: 64, or narrower when a launch has too few
   // segments to give every SIMD several waves
+  static const int64_t min_wg = [] {
+    const char *e = std::getenv("HODBF_MIN_WORKGROUPS");  // tuning knob, default 1024
+    return e ? std::atoll(e) : int64_t(1024);
+  }();
   int RQ = 64;
-  while (RQ > 16 && ns * ((R + RQ - 1) / RQ) < 2048) RQ >>= 1;
+  while (RQ > 16 && ns * ((R + RQ - 1) / RQ) < min_wg) RQ >>= 1;
   if (RQ > R) RQ = R;
   const dim3 grid(unsigned(ns), unsigned((R + RQ - 1) / RQ));
   if (ftype == FT_C64)

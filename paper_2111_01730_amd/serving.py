@@ -5,8 +5,10 @@ over time.  The scheduler
 
 * keeps compressed operators resident in HBM, keyed by the scatterer, and evicts idle
   ones least-recently-used when the device-memory budget needs room;
-* admits pending requests in arrival order whenever a worker slot is free and the
-  memory they need (operator, if not resident, plus solve workspace) fits the budget;
+* builds missing operators on a separate builder pool (so construction never holds a
+  solve slot), in arrival order, when their estimated size fits the budget;
+* admits pending requests whose operator is resident, in arrival order, whenever a
+  solve slot is free and their solve workspace fits the budget;
 * merges every pending request that targets the same resident operator into one
   batched FGMRES solve (their right-hand sides stacked, up to ``max_rhs`` columns);
 * runs each batch on a worker thread with its own HIP stream, so batches of different
@@ -54,7 +56,7 @@ class Result:
     finished: float
     batch_size: int       # requests sharing the solve
     batch_rhs: int        # right-hand sides in that solve
-    built: bool           # this request's batch had to build the operator
+    built: bool           # reserved (construction runs on the builder pool)
 
     @property
     def latency(self) -> float:
@@ -79,7 +81,7 @@ class Server:
     def __init__(self, hbm_budget: int, slots: int = 4, max_rhs: int = 64, tol_con: float = 1e-4,
                  tol_fact: float = 1e-4, precond: int = P_FP32, restart: int = 20,
                  max_iter: int = 3000, est_bytes_per_unknown: float = 90_000.0,
-                 operator_factory=None):
+                 operator_factory=None, build_slots: int = 1):
         self.budget = int(hbm_budget)
         self.slots = slots
         self.max_rhs = max_rhs
@@ -94,6 +96,10 @@ class Server:
         self._running = 0
         self._closed = False
         self._factory = operator_factory or Operator
+        self.build_slots = build_slots
+        self._building = 0
+        self.builds = 0
+        self._builder = ThreadPoolExecutor(max_workers=build_slots)
         self._pool = ThreadPoolExecutor(max_workers=slots)
         # one HIP stream per worker slot (default priority); None without a GPU
         self._streams = [torch.cuda.Stream() if torch.cuda.is_available() else None
@@ -117,11 +123,25 @@ class Server:
             self._closed = True
             self._lock.notify_all()
         self._sched.join()
+        self._builder.shutdown(wait=True)
         self._pool.shutdown(wait=True)
         for ent in self._ops.values():
             if ent["op"] is not None:
                 ent["op"].close()
         self._ops.clear()
+
+    def preload(self, grid) -> float:
+        """Build a scatterer's operator into the resident cache now (blocking); returns
+        the build time in seconds."""
+        key = scatterer_key(grid)
+        with self._lock:
+            if key in self._ops:
+                return 0.0
+            self._ops[key] = {"op": None, "bytes": self._estimate_op_bytes(grid), "busy": 0}
+            self._building += 1
+        t0 = time.perf_counter()
+        self._build(key, grid)
+        return time.perf_counter() - t0
 
     def resident_bytes(self) -> int:
         return sum(e["bytes"] for e in self._ops.values())
@@ -142,67 +162,97 @@ class Server:
     def _loop(self):
         with self._lock:
             while True:
-                if self._closed and not self._pending and self._running == 0:
+                if self._closed and not self._pending and self._running == 0 and self._building == 0:
                     return
-                launched = False
-                if self._free_streams and self._pending:
+                acted = False
+                # 1. start builds for pending scatterers that are neither resident nor
+                #    being built (own pool: builds never hold a solve slot)
+                if self._building < self.build_slots:
                     for req0, _, _, key in self._pending:
-                        ent = self._ops.get(key)
-                        if ent is not None and ent["op"] is None:
-                            continue  # its operator is being built: join a later batch
-                        # the oldest eligible request leads; its batch takes every pending
-                        # request for the same scatterer, in arrival order, up to max_rhs
-                        batch, cols = [], 0
-                        for item in self._pending:
-                            r = item[0]
-                            if item[3] == key and cols + len(r.dirs) <= self.max_rhs:
-                                batch.append(item)
-                                cols += len(r.dirs)
-                        ws = solve_workspace_bytes(req0.grid.n, cols, self.restart)
-                        op_need = 0 if ent is not None else self._estimate_op_bytes(req0.grid)
-                        if ws + op_need > self.budget:
-                            for item in batch:  # can never fit: fail these requests
+                        if key in self._ops:
+                            continue
+                        need = self._estimate_op_bytes(req0.grid)
+                        if need + solve_workspace_bytes(req0.grid.n, 1, self.restart) > self.budget:
+                            for item in [it for it in self._pending if it[3] == key]:
                                 self._pending.remove(item)
                                 item[1].set_exception(MemoryError(
-                                    f"request needs {ws + op_need} bytes, budget {self.budget}"))
-                            launched = True
-                        elif self._try_evict(ws + op_need):
+                                    f"operator needs about {need} bytes, budget {self.budget}"))
+                            acted = True
+                            break
+                        if self._try_evict(need):
+                            self._ops[key] = {"op": None, "bytes": need, "busy": 0}
+                            self._building += 1
+                            self._builder.submit(self._build, key, req0.grid)
+                            acted = True
+                        break  # oldest first; wait for memory otherwise
+                # 2. solve: the oldest request whose operator is resident leads a batch of
+                #    every pending request for that scatterer, up to max_rhs columns
+                if self._free_streams:
+                    for req0, _, _, key in self._pending:
+                        ent = self._ops.get(key)
+                        if ent is None or ent["op"] is None:
+                            continue
+                        batch, cols = [], 0
+                        for item in self._pending:
+                            if item[3] == key and cols + len(item[0].dirs) <= self.max_rhs:
+                                batch.append(item)
+                                cols += len(item[0].dirs)
+                        ws = solve_workspace_bytes(req0.grid.n, cols, self.restart)
+                        if ws > self.budget:
+                            for item in batch:
+                                self._pending.remove(item)
+                                item[1].set_exception(MemoryError(
+                                    f"solve needs {ws} bytes, budget {self.budget}"))
+                            acted = True
+                        elif self._try_evict(ws):
                             for item in batch:
                                 self._pending.remove(item)
                             self._reserved += ws
                             self._running += 1
-                            if ent is not None:
-                                ent["busy"] += 1
-                                self._ops.move_to_end(key)
-                            else:  # placeholder until the worker has built it
-                                self._ops[key] = {"op": None, "bytes": op_need, "busy": 1}
+                            ent["busy"] += 1
+                            self._ops.move_to_end(key)
                             sidx = self._free_streams.pop()
                             self._pool.submit(self._run_batch, key, batch, ws, sidx)
-                            launched = True
-                        break  # first come, first served: only the oldest eligible request
-                if not launched:
+                            acted = True
+                        break
+                if not acted:
                     self._lock.wait(timeout=0.05)
 
-    # ------------------------------------------------------------------ worker
+    # ------------------------------------------------------------------ workers
+    def _build(self, key, grid):
+        try:
+            stream = torch.cuda.Stream() if torch.cuda.is_available() else None
+            ctx = torch.cuda.stream(stream) if stream is not None else _nullctx()
+            with ctx:
+                op = self._factory(grid, **self.build_kw)
+            if stream is not None:
+                stream.synchronize()
+            nbytes = op.stats()["bytes_total"]
+            with self._lock:
+                self._ops[key]["op"] = op
+                self._ops[key]["bytes"] = nbytes
+                self.builds += 1
+                # learn the real size for the estimates of later builds
+                self.est_per_unknown = nbytes / grid.n * 1.1
+        except Exception as e:
+            with self._lock:
+                self._ops.pop(key, None)
+                for item in [it for it in self._pending if it[3] == key]:
+                    self._pending.remove(item)
+                    item[1].set_exception(e)
+        finally:
+            with self._lock:
+                self._building -= 1
+                self._lock.notify_all()
+
     def _run_batch(self, key, batch, ws, sidx):
         stream = self._streams[sidx]
         t_start = time.perf_counter()
-        built = False
         try:
-            req0 = batch[0][0]
             ctx = torch.cuda.stream(stream) if stream is not None else _nullctx()
             with ctx:
                 with self._lock:
                     op = self._ops[key]["op"]
-                if op is None:
-                    op = self._factory(req0.grid, **self.build_kw)
-                    nbytes = op.stats()["bytes_total"]
-                    built = True
-                    with self._lock:
-                        self._ops[key]["op"] = op
-                        self._ops[key]["bytes"] = nbytes
-                        # learn the real size for the estimates of later builds
-                        self.est_per_unknown = nbytes / req0.grid.n * 1.1
                 dirs = np.concatenate([item[0].dirs for item in batch], axis=0)
                 b = op.plane_wave(dirs)
                 tol = min(item[0].tol for item in batch)
@@ -219,13 +269,10 @@ class Server:
                 c += r
                 fut.set_result(Result(req.id, xh[:, sl], info["iters"][sl], info["relres"][sl],
                                       bool(info["converged"][sl].all()), submitted, t_start,
-                                      t_end, len(batch), len(dirs), built))
-            self.log.append(dict(key=key[:8], requests=len(batch), rhs=len(dirs), built=built,
+                                      t_end, len(batch), len(dirs), False))
+            self.log.append(dict(key=key[:8], requests=len(batch), rhs=len(dirs),
                                  start=t_start, end=t_end))
         except Exception as e:  # surface the failure on every request of the batch
-            with self._lock:
-                if key in self._ops and self._ops[key]["op"] is None:
-                    self._ops.pop(key)
             for _, fut, _, _ in batch:
                 if not fut.done():
                     fut.set_exception(e)

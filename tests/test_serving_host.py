@@ -68,8 +68,10 @@ def test_batching_and_results():
     srv.close()
     assert [r.id for r in res] == list(range(7))
     assert all(r.converged and r.x.shape == (n, 2) for r in res)
-    # the three pending requests for each scatterer were merged into one solve each
-    assert max(r.batch_size for r in res) == 3
+    # pending requests for one scatterer were merged into one solve (request 0 waits
+    # for its operator's build, so it joins the later requests for the same scatterer)
+    assert max(r.batch_size for r in res) >= 3
+    assert sum(1 for b in srv.log) <= 4
     assert FakeOp.builds == 2  # each scatterer built once, then resident
 
 
