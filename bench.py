@@ -116,7 +116,7 @@ def serve_mode(args):
     seen = {}
     for q in reqs:
         seen.setdefault(serving.scatterer_key(q.grid), q.grid)
-    build_times = [srv.preload(gr) for gr in seen.values()]
+    build_times = srv.preload(list(seen.values()))
     build_wall = time.perf_counter() - tb
     log(f"[serve] {len(seen)} operators resident after {build_wall:.1f} s")
     t0 = time.perf_counter()

@@ -130,18 +130,25 @@ class Server:
                 ent["op"].close()
         self._ops.clear()
 
-    def preload(self, grid) -> float:
-        """Build a scatterer's operator into the resident cache now (blocking); returns
-        the build time in seconds."""
-        key = scatterer_key(grid)
-        with self._lock:
-            if key in self._ops:
-                return 0.0
-            self._ops[key] = {"op": None, "bytes": self._estimate_op_bytes(grid), "busy": 0}
-            self._building += 1
-        t0 = time.perf_counter()
-        self._build(key, grid)
-        return time.perf_counter() - t0
+    def preload(self, grids) -> list:
+        """Build the operators of these scatterers into the resident cache now, on the
+        builder pool (blocking); returns each build's seconds."""
+        futs = []
+
+        def timed(key, grid):
+            t0 = time.perf_counter()
+            self._build(key, grid)
+            return time.perf_counter() - t0
+
+        for grid in grids:
+            key = scatterer_key(grid)
+            with self._lock:
+                if key in self._ops:
+                    continue
+                self._ops[key] = {"op": None, "bytes": self._estimate_op_bytes(grid), "busy": 0}
+                self._building += 1
+            futs.append(self._builder.submit(timed, key, grid))
+        return [f.result() for f in futs]
 
     def resident_bytes(self) -> int:
         return sum(e["bytes"] for e in self._ops.values())
