@@ -34,6 +34,20 @@ WORKLOAD = "c2_batched_32"
 TOL_SOL = 1e-4
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+# HBM bytes of one forward apply of this workload, from the FETCH_SIZE / WRITE_SIZE
+# counter runs recorded in profiles/grouped_mfma_f32_forward_c2_r64_traffic.md (scaled
+# by a 256 MiB copy); valid only while the kernel and packing sources are unchanged.
+MEASURED_TRAFFIC = {"sources_sha256": "b10da65ef67cac988be05300b0e1ed52d923f4da34353d3a36fc1938324a55fa",
+                    "bytes_per_apply": 1608652161.8 + 487268240.0, "launches_per_apply": 10}
+
+
+def sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "pack.cpp"):
+        with open(os.path.join(ROOT, "paper_2111_01730_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def log(*a):
@@ -265,7 +279,30 @@ def main():
                           f"solves/s = 1 / (ms/step x {per_col:.1f} steps per column, the mean "
                           f"iteration count of the GPU batched solve)")}
 
-    ach = flops_fwd / t_fwd / 1e12
+    # roofline of the dominant kernel (the grouped MFMA kernel of the forward apply):
+    # algorithmic flops 8 R E_Z and bytes 8 E_Z (factors) + 8 R sum(m + n) (vectors)
+    launches = st["fwd_stages"]
+    bytes_fwd = 8.0 * st["entries_fwd"] + 8.0 * R * st["io_rows_fwd"]
+    ai = flops_fwd / bytes_fwd
+    ridge = PEAK_FP32_MFMA_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)
+    traffic = None
+    if sources_sha256() == MEASURED_TRAFFIC["sources_sha256"]:
+        traffic = MEASURED_TRAFFIC["bytes_per_apply"] / MEASURED_TRAFFIC["launches_per_apply"]
+    if ai < ridge:
+        ach = bytes_fwd / t_fwd / 1e9
+        roof = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": ach / PEAK_HBM_GBS}
+    else:
+        ach = flops_fwd / t_fwd / 1e12
+        roof = {"bound": "mfma", "achieved": ach, "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / PEAK_FP32_MFMA_TFLOPS}
+    roof.update({"traffic": traffic, "traffic_unit": "bytes per launch",
+                 "algorithmic_bytes_per_launch": bytes_fwd / launches,
+                 "algorithmic_flops_per_launch": flops_fwd / launches,
+                 "arithmetic_intensity": ai, "ridge": ridge,
+                 "tflops": flops_fwd / t_fwd / 1e12, "mfma_frac": flops_fwd / t_fwd / 1e12 / PEAK_FP32_MFMA_TFLOPS,
+                 "kernel": "k_grouped_mfma_f32 (forward apply, all launches)",
+                 "launches_per_apply": launches, "avg_launch_us": t_fwd / launches * 1e6})
     out = {
         "metric": "HOD-BF apply GFLOP/s + solves/sec at 1e-4 rel. residual, mixed vs plain FP32",
         "value": solves_per_s,
@@ -298,10 +335,7 @@ def main():
         "entries_fwd": st["entries_fwd"],
         "entries_pre": st["entries_pre"],
         "max_rank": st["max_rank"],
-        "roofline": {"bound": "mfma", "achieved": ach, "peak": PEAK_FP32_MFMA_TFLOPS,
-                     "unit": "TFLOP/s", "frac": ach / PEAK_FP32_MFMA_TFLOPS, "traffic": None,
-                     "kernel": "k_grouped_mfma_f32 (forward apply, all launches)",
-                     "launches_per_apply": st["fwd_stages"]},
+        "roofline": roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

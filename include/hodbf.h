@@ -181,6 +181,9 @@ typedef struct {
   double build_seconds;      /* wall time of the forward construction */
   double precond_seconds;    /* wall time of the preconditioner construction */
   int64_t id_count;          /* interpolative decompositions computed */
+  int64_t io_rows_fwd;       /* sum over stored blocks of (rows + cols) of Z_con: one apply
+                                reads and writes 8 * nrhs * io_rows_fwd vector bytes */
+  int64_t io_rows_pre;       /* the same for the preconditioner */
 } hodbf_stats_t;
 
 hodbf_status hodbf_stats(const hodbf_op *op, hodbf_stats_t *st);
