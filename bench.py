@@ -149,13 +149,68 @@ def serve_mode(args):
     return 0
 
 
+def config_mode(args):
+    """One named workload end to end: build, forward and preconditioner applies, and a
+    batched FP32-preconditioned solve (iterations, time, true residual)."""
+    import torch
+
+    from paper_2111_01730_amd.hodbf import P_FP32, Operator
+    from synth import config
+    cfg = config(args.config)
+    g = cfg["grid"]
+    R = cfg["nrhs"]
+    tol = cfg["tol"]
+    t0 = time.perf_counter()
+    op = Operator(g, tol_con=tol, tol_fact=args.tol_fact, precond=P_FP32,
+                  precond_min_level=args.precond_min_level, seed=cfg["seed"])
+    build_s = time.perf_counter() - t0
+    st = op.stats()
+    log(f"[build] {build_s:.1f}s {st}")
+    b = op.plane_wave(cfg["dirs"])
+    perm = torch.as_tensor(op.perm().astype(np.int64), device="cuda")
+    xt = b[perm].to(torch.complex64).contiguous()
+    times = {}
+    for name, which in (("forward", 0), ("precond_fp32", 2)):
+        for _ in range(2):
+            op.apply_tree(xt, which)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        for _ in range(5):
+            op.apply_tree(xt, which)
+        torch.cuda.synchronize()
+        times[name] = (time.perf_counter() - ta) / 5
+    tsol = time.perf_counter()
+    x, info = op.solve(b, tol=tol, restart=args.restart, max_iter=args.max_iter, use_precond="fp32")
+    torch.cuda.synchronize()
+    solve_s = time.perf_counter() - tsol
+    out = {"mode": "config", "config": args.config, "n": g.n, "nrhs": R, "tol_con": tol,
+           "tol_fact": args.tol_fact, "precond_min_level": args.precond_min_level,
+           "build_s": build_s, "forward_build_s": st["build_seconds"],
+           "precond_build_s": st["precond_seconds"], "entries_fwd": st["entries_fwd"],
+           "entries_pre": st["entries_pre"], "max_rank": st["max_rank"],
+           "bytes_total": st["bytes_total"],
+           "forward_apply_ms": times["forward"] * 1e3,
+           "forward_gflops": 8.0 * R * st["entries_fwd"] / times["forward"] / 1e9,
+           "precond_apply_ms": times["precond_fp32"] * 1e3,
+           "solve_s": solve_s, "solves_per_s": R / solve_s,
+           "iters_max": int(info["iters"].max()), "iters_mean": float(info["iters"].mean()),
+           "converged": bool(info["converged"].all()), "relres_max": float(info["relres"].max()),
+           "restart": args.restart}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--tol-fact", type=float, default=1e-4)
-    ap.add_argument("--mode", choices=["solve", "apply", "serve"], default="solve")
+    ap.add_argument("--mode", choices=["solve", "apply", "serve", "config"], default="solve")
+    ap.add_argument("--config", default="c3_sphere_64", help="workload of --mode config")
+    ap.add_argument("--precond-min-level", type=int, default=0)
+    ap.add_argument("--restart", type=int, default=20)
+    ap.add_argument("--max-iter", type=int, default=3000)
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-rate", type=float, default=20.0, help="mean arrivals per second")
     ap.add_argument("--serve-sizes", default="16,32", help="cube sides drawn by requests")
@@ -188,6 +243,8 @@ def main():
         return apply_mode(args, cfg, Operator, P_NONE)
     if args.mode == "serve":
         return serve_mode(args)
+    if args.mode == "config":
+        return config_mode(args)
     t0 = time.perf_counter()
     op = Operator(g, tol_con=cfg["tol"], tol_fact=args.tol_fact, precond=P_FP32 | P_BF16 | P_FP16,
                   seed=cfg["seed"])

@@ -11,6 +11,7 @@
 namespace hodbf {
 
 using cd = std::complex<double>;
+using cf = std::complex<float>;
 
 // Error plumbing: internal code throws hodbf::Error; the C ABI catches it.
 struct Error {
@@ -52,10 +53,11 @@ Kernel make_kernel(const Tree &t, const std::vector<cd> &eps_user, double h, dou
 int id_cpqr(cd *M, int m, int n, double chi, std::vector<int> &J, std::vector<cd> &V);
 
 // ---------------------------------------------------------------------------
-// Host plan of one butterfly: factors in FP64, column-major.
+// Host plan of one butterfly: factors column-major, computed in FP64 and kept in
+// complex FP32 (the device copies are FP32 or narrower).
 struct Mat {
   int m = 0, n = 0;
-  std::vector<cd> v;  // m x n column-major
+  std::vector<cf> v;  // m x n column-major
 };
 struct Butterfly {
   int hod_level = 0;   // level of o and s in T_H

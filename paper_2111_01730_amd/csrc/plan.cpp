@@ -177,7 +177,7 @@ void build_butterflies(const EntrySource &src, const Tree &t, std::vector<Butter
             for (int r = 0; r < nr; ++r) M[size_t(c) * nr + r] *= wt[r];
           const int rk = id_cpqr(M.data(), nr, nc, chi, J, V);
           out.m = rk;
-          out.v = V;
+          out.v.assign(V.begin(), V.end());
           sk.resize(rk);
           for (int i = 0; i < rk; ++i) sk[i] = cols[J[i]];
         }

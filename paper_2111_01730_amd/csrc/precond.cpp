@@ -189,10 +189,11 @@ void build_precond(hodbf_op &op, hipStream_t st) {
     const int64_t off = (int64_t(host.size()) + 15) & ~int64_t(15);
     host.resize(size_t(off + int64_t(f.m) * f.n));
     double mx = 0;
-    for (const cd &v : f.v) mx = std::max({mx, std::abs(v.real()), std::abs(v.imag())});
+    for (const cf &v : f.v)
+      mx = std::max({mx, std::abs(double(v.real())), std::abs(double(v.imag()))});
     const float s = mx > 0 ? float(mx) : 1.0f;
     const double inv = 1.0 / double(s);
-    for (size_t e = 0; e < f.v.size(); ++e) host[size_t(off) + e] = f.v[e] * inv;
+    for (size_t e = 0; e < f.v.size(); ++e) host[size_t(off) + e] = cd(f.v[e]) * inv;
     *scale = s;
     return off;
   };
@@ -204,12 +205,13 @@ void build_precond(hodbf_op &op, hipStream_t st) {
     for (int64_t g = 0; g < nleaf; ++g) {
       const int32_t lo = t.node_lo(LH, g), hi = t.node_hi(LH, g);
       const int m = hi - lo;
+      std::vector<cd> Dv(size_t(m) * m);
+      for (int c = 0; c < m; ++c)
+        for (int r = 0; r < m; ++r) Dv[size_t(c) * m + r] = op.ker.entry(lo + r, lo + c);
+      small_inverse(Dv, m);
       Mat D;
       D.m = D.n = m;
-      D.v.resize(size_t(m) * m);
-      for (int c = 0; c < m; ++c)
-        for (int r = 0; r < m; ++r) D.v[size_t(c) * m + r] = op.ker.entry(lo + r, lo + c);
-      small_inverse(D.v, m);
+      D.v.assign(Dv.begin(), Dv.end());
       Pair pr{};
       pr.f_off = put(D, &pr.scale);
       pr.in_row = lo;
@@ -270,10 +272,11 @@ void build_precond(hodbf_op &op, hipStream_t st) {
           Mat &B = bf.B[size_t(a)];
           B.m = r1 - r0;
           B.n = int(sk.size());
-          B.v.resize(size_t(B.m) * B.n);
+          std::vector<cd> Bv(size_t(B.m) * B.n);
           std::vector<int32_t> rows(static_cast<size_t>(B.m));
           for (int i = 0; i < B.m; ++i) rows[size_t(i)] = r0 + i;
-          if (B.n) src.fill(rows.data(), B.m, sk.data(), B.n, B.v.data());
+          if (B.n) src.fill(rows.data(), B.m, sk.data(), B.n, Bv.data());
+          B.v.assign(Bv.begin(), Bv.end());
         }
         for (auto &v : bf.V0) maxr = std::max(maxr, v.m);
         for (int lv = 1; lv <= bf.L; ++lv)
