@@ -188,6 +188,7 @@ void build_butterflies(const EntrySource &src, const Tree &t, std::vector<Butter
     }
     for (size_t k = 0; k < bfs.size(); ++k)
       if (bfs[k].L >= l) skel[k].swap(nskel[k]);
+    if (jobs.size() >= 100000) logf("  butterfly level %d: %zu IDs done", l, jobs.size());
   }
   for (size_t k = 0; k < bfs.size(); ++k) {
     Butterfly &bf = bfs[k];

@@ -240,7 +240,7 @@ void build_precond(hodbf_op &op, hipStream_t st) {
     for (int64_t tau = 0; tau < (int64_t(1) << l); ++tau) {
       std::vector<cd> Xh;
       dense_x(op, rh, l, tau, Xh, st);
-      if (l <= 2)
+      if (t.node_hi(l, tau) - t.node_lo(l, tau) >= 4096)
         logf("  dense X for level %d node %lld ready, %.2f s", l, (long long)tau,
              std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
       DenseSource src;
