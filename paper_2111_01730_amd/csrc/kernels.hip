@@ -87,8 +87,10 @@ __device__ inline float2 load_factor(const FF16 *F, int64_t idx) {
                      __half2float(__ushort_as_half((unsigned short)(w >> 16))));
 }
 
-// Small-R grouped GEMM: one wave per segment.  Lanes split the m <= 64 rows and a few
-// k-groups; factor columns are read coalesced, input values broadcast.
+// Small-R grouped GEMM: one wave per segment.  Lanes split the m <= 64 rows and
+// G = 64 / mp k-groups; factor columns are read coalesced, input values broadcast.
+// Each lane keeps 8 factor loads in flight (columns k, k + G, ..., k + 7G) so the
+// factor stream is not serialised on memory latency.
 template <typename FT>
 __global__ __launch_bounds__(256) void k_grouped_gemv(const Seg *__restrict__ segs,
                                                       const Pair *__restrict__ pairs,
@@ -97,6 +99,7 @@ __global__ __launch_bounds__(256) void k_grouped_gemv(const Seg *__restrict__ se
                                                       const float2 *__restrict__ T,
                                                       float2 *__restrict__ OUT, int R,
                                                       int beta, int64_t nseg) {
+  constexpr int U = 8;
   const int64_t w = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
   if (w >= nseg) return;
   const int lane = threadIdx.x & 63;
@@ -105,24 +108,35 @@ __global__ __launch_bounds__(256) void k_grouped_gemv(const Seg *__restrict__ se
   const int mp = m <= 16 ? 16 : (m <= 32 ? 32 : 64);
   const int G = 64 / mp;
   const int i = lane % mp, g = lane / mp;
+  const bool rok = i < m;
   for (int q0 = 0; q0 < R; q0 += 4) {
     const int nq = R - q0 < 4 ? R - q0 : 4;
     float ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
     for (int p = sg.p0; p < sg.p1; ++p) {
       const Pair pr = pairs[p];
       const float2 *in = (pr.in_buf ? T : X) + int64_t(pr.in_row) * R + q0;
-      for (int k = g; k < pr.n; k += G) {
-        float2 a = i < m ? load_factor(F, pr.f_off + int64_t(k) * pr.lda + i)
-                         : make_float2(0.f, 0.f);
-        a.x *= pr.scale;
-        a.y *= pr.scale;
-        const float2 *xk = in + int64_t(k) * R;
+      const FT *A = F + pr.f_off;
+      for (int k0 = g; k0 < pr.n; k0 += G * U) {
+        float2 a[U];
 #pragma unroll
-        for (int qq = 0; qq < 4; ++qq) {
-          if (qq < nq) {
-            const float2 x = xk[qq];
-            ar[qq] += a.x * x.x - a.y * x.y;
-            ai[qq] += a.x * x.y + a.y * x.x;
+        for (int u = 0; u < U; ++u) {
+          const int k = k0 + u * G;
+          a[u] = (rok && k < pr.n) ? load_factor(A, int64_t(k) * pr.lda + i) : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int k = k0 + u * G;
+          if (k < pr.n) {
+            const float2 *xk = in + int64_t(k) * R;
+            const float2 av = make_float2(a[u].x * pr.scale, a[u].y * pr.scale);
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq) {
+              if (qq < nq) {
+                const float2 x = xk[qq];
+                ar[qq] += av.x * x.x - av.y * x.y;
+                ai[qq] += av.x * x.y + av.y * x.x;
+              }
+            }
           }
         }
       }
@@ -134,7 +148,7 @@ __global__ __launch_bounds__(256) void k_grouped_gemv(const Seg *__restrict__ se
         ai[qq] += __shfl_xor(ai[qq], off);
       }
     }
-    if (g == 0 && i < m) {
+    if (g == 0 && rok) {
       float2 *o = OUT + int64_t(sg.out_row + i) * R + q0;
 #pragma unroll
       for (int qq = 0; qq < 4; ++qq) {
