@@ -195,9 +195,10 @@ hodbf_status hodbf_stats(const hodbf_op *op, hodbf_stats_t *st);
  *        3 preconditioner block table, 4 preconditioner values of the FP32 copy,
  *        5 of the BF16 copy, 6 of the FP16 copy (each as complex FP32, block
  *          scales applied).
- * Block tables are int64 rows of 11: kind (0 dense leaf, 1 V0, 2 W, 3 B),
+ * Block tables are int64 rows of 12: kind (0 dense leaf, 1 V0, 2 W, 3 B),
  * hod level l, node i, child row ca, child col cb, butterfly level, a, b, rows m,
- * cols n, offset (complex elements into the values, column-major m x n).
+ * cols n, offset, lda: element (i, k) of the block is value [offset + k lda + i]
+ * (complex elements; blocks that share an input are stored stacked, lda >= m).
  * Call with buf == NULL to get the size in *bytes; E_ARG if *bytes is too small.
  */
 hodbf_status hodbf_export(const hodbf_op *op, int32_t which, void *buf, size_t *bytes);

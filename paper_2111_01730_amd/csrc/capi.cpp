@@ -99,8 +99,8 @@ void scratch_free(void *p, hipStream_t st) {
 void run_program(const Program &prog, const void *F, int ftype, const float2 *X, float2 *T,
                  float2 *OUT, int R, hipStream_t st) {
   for (const Launch &ln : prog.launches) {
-    launch_grouped(prog.segs.as<Seg>(), prog.pairs.as<Pair>(), ln.s0, ln.ns, F, ftype, X, T,
-                   ln.out ? OUT : T, R, ln.beta, st);
+    launch_grouped(prog.segs.as<Seg>(), prog.pairs.as<Pair>(), prog.rowmap.as<RowMap>(), ln.s0,
+                   ln.ns, ln.cls, F, ftype, X, T, ln.out ? OUT : T, R, ln.beta, st);
   }
 }
 
@@ -440,10 +440,12 @@ static void export_arena(const DevBuf &a, int ft, const std::vector<BlockRec> *t
     for (size_t r = 0; r < table->size(); ++r) {
       const BlockRec &b = (*table)[r];
       const float s = (*scales)[r];
-      for (int64_t e = 0; e < b.m * b.n; ++e) {
-        o[2 * (b.off + e)] *= s;
-        o[2 * (b.off + e) + 1] *= s;
-      }
+      for (int64_t k = 0; k < b.n; ++k)
+        for (int64_t i = 0; i < b.m; ++i) {
+          const int64_t e = b.off + k * b.lda + i;
+          o[2 * e] *= s;
+          o[2 * e + 1] *= s;
+        }
     }
   *bytes = need;
 }
@@ -514,19 +516,19 @@ hodbf_status hodbf_plan_probe(const hodbf_build_params *params, int32_t which, v
       for (auto &bf : fp.bfs) {
         for (int64_t b = 0; b < int64_t(bf.V0.size()); ++b) {
           const Mat &f = bf.V0[size_t(b)];
-          g_probe_table.push_back({1, bf.hod_level, bf.oi, 0, 0, 0, 0, b, f.m, f.n, put(f)});
+          g_probe_table.push_back({1, bf.hod_level, bf.oi, 0, 0, 0, 0, b, f.m, f.n, put(f), f.m});
         }
         for (int l = 1; l <= bf.L; ++l) {
           const int64_t nb = int64_t(1) << (bf.L - l);
           for (int64_t e = 0; e < int64_t(bf.W[l].size()); ++e) {
             const Mat &f = bf.W[l][size_t(e)];
-            g_probe_table.push_back({2, bf.hod_level, bf.oi, 0, 0, l, e / nb, e % nb, f.m, f.n, put(f)});
+            g_probe_table.push_back({2, bf.hod_level, bf.oi, 0, 0, l, e / nb, e % nb, f.m, f.n, put(f), f.m});
           }
         }
         for (int64_t a = 0; a < int64_t(bf.bskel.size()); ++a) {
           const auto &sk = bf.bskel[size_t(a)];
           g_probe_table.push_back({3, bf.hod_level, bf.oi, 0, 0, bf.L, a, 0, 0, int64_t(sk.size()),
-                                   int64_t(g_probe_skel.size())});
+                                   int64_t(g_probe_skel.size()), 0});
           g_probe_skel.insert(g_probe_skel.end(), sk.begin(), sk.end());
         }
       }

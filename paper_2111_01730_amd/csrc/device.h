@@ -7,11 +7,19 @@
 
 namespace hodbf {
 
-// One output segment of a grouped complex GEMM: rows [out_row, out_row + m) of the
-// output buffer (m <= 64) receive the sum over pairs [p0, p1) of A_p * in_p.
+// One output tile of a grouped complex GEMM: m <= 128 rows, the sum over pairs
+// [p0, p1) of A_p * in_p.  Its rows are scattered by the row map entries
+// [map0, map1) (sorted by start): local row r goes to out_row + r - start of the last
+// entry with start <= r, so one tile can hold several stacked blocks that read the
+// same input rows.
 struct Seg {
-  int32_t out_row, m, p0, p1;
+  int32_t m, p0, p1, map0, map1, pad0, pad1, pad2;
 };
+struct RowMap {
+  int32_t start, out_row;
+};
+constexpr int kTileRows = 64;  // rows of one workgroup tile; leaves hold at most 64 rows
+constexpr int kRowClasses = kTileRows / 16;  // tiles of 1..kRowClasses 16-row MFMA tiles
 
 // A factor block (column-major, element (i, k) at f_off + k * lda + i, stored values
 // multiplied by scale on load) times the input rows [in_row, in_row + n) of buffer X
@@ -36,9 +44,11 @@ enum FactorType { FT_C64 = 0, FT_BF16 = 1, FT_F16 = 2 };
 
 // Grouped GEMM over segs[s0, s0 + ns): OUT(seg rows) = beta * OUT + sum A * in.
 // X, T, OUT: complex FP32 RHS-interleaved (element (row, q) at row * R + q).
-void launch_grouped(const Seg *segs, const Pair *pairs, int64_t s0, int64_t ns, const void *F,
-                    int ftype, const float2 *X, const float2 *T, float2 *OUT, int R, int beta,
-                    hipStream_t st);
+// The segments of a launch are sorted by row-tile count; cls[c] (c = 0..kRowClasses) is
+// the first segment (relative to s0) with more than c row tiles, cls[kRowClasses] = ns.
+void launch_grouped(const Seg *segs, const Pair *pairs, const RowMap *rowmap, int64_t s0,
+                    int64_t ns, const int64_t *cls, const void *F, int ftype, const float2 *X,
+                    const float2 *T, float2 *OUT, int R, int beta, hipStream_t st);
 
 void launch_entries(const EntryJob *jobs, int64_t njobs, const int32_t *cols, const short4 *xyz,
                     const double2 *inv_eps, const double2 *kappa, double kh, double2 k2S,

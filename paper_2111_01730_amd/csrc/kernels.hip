@@ -75,25 +75,44 @@ struct FBF16 {
 struct FF16 {
   uint32_t v;
 };
-__device__ inline float2 load_factor(const float2 *F, int64_t idx) { return F[idx]; }
+// Loads through global-address-space pointers (global_load rather than flat_load).
+typedef float gfloat2v __attribute__((ext_vector_type(2)));
+__device__ inline float2 ldg_f2(const float2 *p, int64_t idx) {
+  const gfloat2v v = ((const __attribute__((address_space(1))) gfloat2v *)p)[idx];
+  return make_float2(v.x, v.y);
+}
+__device__ inline uint32_t ldg_u32(const uint32_t *p, int64_t idx) {
+  return ((const __attribute__((address_space(1))) uint32_t *)p)[idx];
+}
+__device__ inline float2 load_factor(const float2 *F, int64_t idx) { return ldg_f2(F, idx); }
 __device__ inline float bf16_to_f(uint32_t h) { return __uint_as_float(h << 16); }
 __device__ inline float2 load_factor(const FBF16 *F, int64_t idx) {
-  const uint32_t w = F[idx].v;
+  const uint32_t w = ldg_u32(reinterpret_cast<const uint32_t *>(F), idx);
   return make_float2(bf16_to_f(w & 0xFFFFu), bf16_to_f(w >> 16));
 }
 __device__ inline float2 load_factor(const FF16 *F, int64_t idx) {
-  const uint32_t w = F[idx].v;
+  const uint32_t w = ldg_u32(reinterpret_cast<const uint32_t *>(F), idx);
   return make_float2(__half2float(__ushort_as_half((unsigned short)(w & 0xFFFFu))),
                      __half2float(__ushort_as_half((unsigned short)(w >> 16))));
 }
 
-// Small-R grouped GEMM: one wave per segment.  Lanes split the m <= 64 rows and
-// G = 64 / mp k-groups; factor columns are read coalesced, input values broadcast.
+// Output row of local row r of a tile: the last row-map entry with start <= r.
+__device__ __forceinline__ int64_t mapped_row(const RowMap *__restrict__ rm, int map0, int map1,
+                                              int r) {
+  int e = map0;
+  for (int k = map0 + 1; k < map1; ++k)
+    if (rm[k].start <= r) e = k;
+  return int64_t(rm[e].out_row) + (r - rm[e].start);
+}
+
+// Small-R grouped GEMM: one wave per tile, 64 rows at a time.  Lanes split the rows
+// and G = 64 / mp k-groups; factor columns are read coalesced, input values broadcast.
 // Each lane keeps 8 factor loads in flight (columns k, k + G, ..., k + 7G) so the
 // factor stream is not serialised on memory latency.
 template <typename FT>
 __global__ __launch_bounds__(256) void k_grouped_gemv(const Seg *__restrict__ segs,
                                                       const Pair *__restrict__ pairs,
+                                                      const RowMap *__restrict__ rowmap,
                                                       const FT *__restrict__ F,
                                                       const float2 *__restrict__ X,
                                                       const float2 *__restrict__ T,
@@ -104,62 +123,65 @@ __global__ __launch_bounds__(256) void k_grouped_gemv(const Seg *__restrict__ se
   if (w >= nseg) return;
   const int lane = threadIdx.x & 63;
   const Seg sg = segs[w];
-  const int m = sg.m;
-  const int mp = m <= 16 ? 16 : (m <= 32 ? 32 : 64);
-  const int G = 64 / mp;
-  const int i = lane % mp, g = lane / mp;
-  const bool rok = i < m;
-  for (int q0 = 0; q0 < R; q0 += 4) {
-    const int nq = R - q0 < 4 ? R - q0 : 4;
-    float ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
-    for (int p = sg.p0; p < sg.p1; ++p) {
-      const Pair pr = pairs[p];
-      const float2 *in = (pr.in_buf ? T : X) + int64_t(pr.in_row) * R + q0;
-      const FT *A = F + pr.f_off;
-      for (int k0 = g; k0 < pr.n; k0 += G * U) {
-        float2 a[U];
+  for (int rb = 0; rb < sg.m; rb += 64) {
+    const int m = sg.m - rb < 64 ? sg.m - rb : 64;
+    const int mp = m <= 16 ? 16 : (m <= 32 ? 32 : 64);
+    const int G = 64 / mp;
+    const int i = lane % mp, g = lane / mp;
+    const bool rok = i < m;
+    for (int q0 = 0; q0 < R; q0 += 4) {
+      const int nq = R - q0 < 4 ? R - q0 : 4;
+      float ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
+      for (int p = sg.p0; p < sg.p1; ++p) {
+        const Pair pr = pairs[p];
+        const float2 *in = (pr.in_buf ? T : X) + int64_t(pr.in_row) * R + q0;
+        const FT *A = F + pr.f_off + rb;
+        for (int k0 = g; k0 < pr.n; k0 += G * U) {
+          float2 a[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int k = k0 + u * G;
-          a[u] = (rok && k < pr.n) ? load_factor(A, int64_t(k) * pr.lda + i) : make_float2(0.f, 0.f);
-        }
+          for (int u = 0; u < U; ++u) {
+            const int k = k0 + u * G;
+            a[u] = (rok && k < pr.n) ? load_factor(A, int64_t(k) * pr.lda + i)
+                                     : make_float2(0.f, 0.f);
+          }
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int k = k0 + u * G;
-          if (k < pr.n) {
-            const float2 *xk = in + int64_t(k) * R;
-            const float2 av = make_float2(a[u].x * pr.scale, a[u].y * pr.scale);
+          for (int u = 0; u < U; ++u) {
+            const int k = k0 + u * G;
+            if (k < pr.n) {
+              const float2 *xk = in + int64_t(k) * R;
+              const float2 av = make_float2(a[u].x * pr.scale, a[u].y * pr.scale);
 #pragma unroll
-            for (int qq = 0; qq < 4; ++qq) {
-              if (qq < nq) {
-                const float2 x = xk[qq];
-                ar[qq] += av.x * x.x - av.y * x.y;
-                ai[qq] += av.x * x.y + av.y * x.x;
+              for (int qq = 0; qq < 4; ++qq) {
+                if (qq < nq) {
+                  const float2 x = xk[qq];
+                  ar[qq] += av.x * x.x - av.y * x.y;
+                  ai[qq] += av.x * x.y + av.y * x.x;
+                }
               }
             }
           }
         }
       }
-    }
-    for (int off = mp; off < 64; off <<= 1) {
+      for (int off = mp; off < 64; off <<= 1) {
 #pragma unroll
-      for (int qq = 0; qq < 4; ++qq) {
-        ar[qq] += __shfl_xor(ar[qq], off);
-        ai[qq] += __shfl_xor(ai[qq], off);
+        for (int qq = 0; qq < 4; ++qq) {
+          ar[qq] += __shfl_xor(ar[qq], off);
+          ai[qq] += __shfl_xor(ai[qq], off);
+        }
       }
-    }
-    if (g == 0 && rok) {
-      float2 *o = OUT + int64_t(sg.out_row + i) * R + q0;
+      if (g == 0 && rok) {
+        float2 *o = OUT + mapped_row(rowmap, sg.map0, sg.map1, rb + i) * R + q0;
 #pragma unroll
-      for (int qq = 0; qq < 4; ++qq) {
-        if (qq < nq) {
-          float2 v = make_float2(ar[qq], ai[qq]);
-          if (beta) {
-            const float2 u = o[qq];
-            v.x += u.x;
-            v.y += u.y;
+        for (int qq = 0; qq < 4; ++qq) {
+          if (qq < nq) {
+            float2 v = make_float2(ar[qq], ai[qq]);
+            if (beta) {
+              const float2 u = o[qq];
+              v.x += u.x;
+              v.y += u.y;
+            }
+            o[qq] = v;
           }
-          o[qq] = v;
         }
       }
     }
@@ -173,8 +195,8 @@ __global__ __launch_bounds__(256) void k_grouped_gemv(const Seg *__restrict__ se
 // v_mfma_f32_16x16x4f32: lane l holds A[l % 16][l / 16], B[l / 16][l % 16] and
 // D[4 (l / 16) + v][l % 16].  Four MFMAs consume 8 complex columns: slot kk of MFMA t
 // is real column 4 kk + t, i.e. complex column 2 kk + t / 2, part t % 2.
-// One workgroup owns one segment (<= 64 output rows).  Its output tiles (16 rows x 8
-// right-hand sides) are dealt to the four waves as a cw x rw grid: wave w takes the
+// One workgroup of kWaves waves owns one tile (<= kTileRows output rows).  Its output tiles
+// (16 rows x 8 right-hand sides) are dealt to the waves as a cw x rw grid: wave w takes the
 // column tiles congruent to w % cw and the row tiles congruent to w / cw, so every
 // row count keeps all waves busy and a wave reuses its input fragments across its row
 // tiles.  Factor columns and input rows are streamed in chunks of KC = 16 complex
@@ -182,172 +204,298 @@ __global__ __launch_bounds__(256) void k_grouped_gemv(const Seg *__restrict__ se
 // chunk is fetched into registers while the current one is multiplied.  The chunk
 // loop is instantiated per (row tiles, column tiles) of a wave so that its inner
 // loops have fixed trip counts; every instantiation runs the same barriers.
-constexpr int kKC = 16;  // complex K rows per chunk
-constexpr int kXS = 68;  // LDS stride of an input row (64 + 4 complex: conflict-free reads)
-constexpr int kAS = 72;  // LDS stride of a factor column (64 + 8 complex: conflict-free)
+constexpr int kKC = 16;                 // complex K rows per chunk
+constexpr int kXS = 68;                 // LDS stride of an input row (64 + 4 complex: conflict-free)
+constexpr int kAS = kTileRows + 8;      // LDS stride of a factor column (conflict-free)
+constexpr int kWaves = kTileRows / 16;  // waves per workgroup: one per row tile of a full tile
+constexpr int kThreads = 64 * kWaves;
+constexpr int kXL = kKC * 64 / kThreads;         // input elements per thread and chunk
+constexpr int kAL = kKC * kTileRows / kThreads;  // factor elements per thread and chunk
 
-template <typename FT, int NRI, int NCI>
-__device__ __forceinline__ void grouped_chunks(const Seg sg, const Pair *__restrict__ pairs,
-                                               const FT *__restrict__ F,
+// Where a chunk comes from: a pair's factor block and input rows, restricted to one
+// right-hand-side slice [q0, q0 + rc) and the tile's m rows.  All fields are uniform.
+struct ChunkSrc {
+  int64_t x;  // element offset of input row 0, column q0, in X (xt = 0) or T (xt = 1)
+  int64_t a;  // factor offset of the pair
+  int xt, n, lda, rc, m;
+  float scale;
+};
+
+__device__ __forceinline__ ChunkSrc chunk_src(const Pair &pr, int R, int q0, int rc, int m) {
+  ChunkSrc c;
+  c.x = int64_t(pr.in_row) * R + q0;
+  c.xt = pr.in_buf;
+  c.a = pr.f_off;
+  c.n = pr.n;
+  c.lda = pr.lda;
+  c.rc = rc;
+  c.m = m;
+  c.scale = pr.scale;
+  return c;
+}
+
+
+// Fetch chunk rows [kb, kb + kKC) of a source into registers.  Every lane loads from
+// an in-bounds address (indices clamped to the block); bit i of msk says whether value i
+// (inputs first, then factors) lies inside the block.  Masking and the factor scale are
+// applied when the chunk is written to LDS, so the loads stay in flight until then.
+template <typename FT>
+__device__ __forceinline__ unsigned load_chunk(const ChunkSrc &c, int kb, const FT *__restrict__ F,
                                                const float2 *__restrict__ X,
-                                               const float2 *__restrict__ T,
-                                               float2 *__restrict__ OUT, int R, int beta,
-                                               int q0, int Rc, int wr, int rw, int wc, int cw,
-                                               float2 *xs, float2 *as) {
-  const int m = sg.m;
+                                               const float2 *__restrict__ T, int R,
+                                               float2 (&xr)[kXL], float2 (&ar)[kAL]) {
+  const int tid = threadIdx.x;
+  const float2 *xb = (c.xt ? T : X) + c.x;
+  const FT *ab = F + c.a;
+  unsigned msk = 0;
+#pragma unroll
+  for (int i = 0; i < kXL; ++i) {
+    const int e = tid + kThreads * i;
+    const int hi = kb + (e >> 6), lo = e & 63;  // input row hi, column lo
+    const unsigned off = unsigned(min(hi, c.n - 1)) * unsigned(R) + unsigned(min(lo, c.rc - 1));
+    xr[i] = ldg_f2(xb, off);
+    msk |= unsigned(hi < c.n && lo < c.rc) << i;
+  }
+#pragma unroll
+  for (int i = 0; i < kAL; ++i) {
+    const int e = tid + kThreads * i;
+    const int hi = kb + e / kTileRows, lo = e % kTileRows;  // factor column hi, row lo
+    const unsigned off = unsigned(min(hi, c.n - 1)) * unsigned(c.lda) + unsigned(min(lo, c.m - 1));
+    ar[i] = load_factor(ab, off);
+    msk |= unsigned(hi < c.n && lo < c.m) << (kXL + i);
+  }
+  return msk;
+}
+
+// Work items of one tile class: item it is tile it / nsl with right-hand-side slice
+// it % nsl of RQ (<= 64) columns; this workgroup takes items first, first + stride, ...
+// below end.  The next item's descriptors and first chunk are fetched while the current
+// item's last chunk is multiplied, so a workgroup streams without a gap between tiles.
+// The wave owns NRI row tiles (wr, wr + RW, ...) and NCI column tiles (wc, wc + CW), CW =
+// kWaves / RW; all LDS offsets are compile-time immediates from one lane base address.
+template <typename FT, int NRI, int NCI, int RW>
+__device__ __forceinline__ void class_items(int it, const int end, const int stride, const int nsl,
+                                            const int RQ, const Seg *__restrict__ segs,
+                                            const Pair *__restrict__ pairs,
+                                            const RowMap *__restrict__ rowmap,
+                                            const FT *__restrict__ F,
+                                            const float2 *__restrict__ X,
+                                            const float2 *__restrict__ T,
+                                            float2 *__restrict__ OUT, const int R, const int beta,
+                                            const int wr, const int wc, float2 *xs, float2 *as) {
+  constexpr int CW = kWaves / RW;
   const int tid = threadIdx.x, lane = tid & 63;
   const int i16 = lane & 15;
   const int kk = lane >> 4;
   const int qo = i16 >> 1, op = i16 & 1;
-  const float2 z2 = make_float2(0.f, 0.f);
-  floatx4 acc[NRI > 0 ? NRI * NCI : 1];
-#pragma unroll
-  for (int j = 0; j < (NRI > 0 ? NRI * NCI : 1); ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
-  float2 xr[4], ar[4];
-  int p = sg.p0, k0 = 0;
-  Pair pr = pairs[p];
-#define HODBF_LOAD_CHUNK(PP, KB)                                                              \
-  {                                                                                           \
-    const float2 *xb_ = ((PP).in_buf ? T : X) + int64_t((PP).in_row + (KB)) * R + q0;         \
-    const FT *A_ = F + (PP).f_off;                                                            \
-    _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                           \
-      const int e = tid + 256 * i;                                                            \
-      const int hi = e >> 6, lo = e & 63; /* x: row hi, column lo; A: column hi, row lo */    \
-      const bool kin = (KB) + hi < (PP).n;                                                    \
-      xr[i] = (kin && lo < Rc) ? xb_[int64_t(hi) * R + lo] : z2;                             \
-      float2 a_ = (kin && lo < m) ? load_factor(A_, int64_t((KB) + hi) * (PP).lda + lo) : z2; \
-      a_.x *= (PP).scale;                                                                     \
-      a_.y *= (PP).scale;                                                                     \
-      ar[i] = a_;                                                                             \
-    }                                                                                         \
-  }
-  HODBF_LOAD_CHUNK(pr, k0);
+  const float2 *xl = xs + 2 * kk * kXS + wc * 8 + qo;   // this lane's input fragment base
+  const float2 *al = as + 2 * kk * kAS + wr * 16 + i16;  // this lane's factor fragment base
+  Seg sg = segs[it / nsl];
+  int q0 = (it % nsl) * RQ;
+  int Rc = min(R - q0, RQ);
+  ChunkSrc cur = chunk_src(pairs[sg.p0], R, q0, Rc, sg.m);
+  float2 xr[kXL], ar[kAL];
+  unsigned msk = load_chunk<FT>(cur, 0, F, X, T, R, xr, ar);
+  float lscale = cur.scale;  // factor scale of the chunk held in xr / ar
   while (true) {
-    __syncthreads();  // previous chunk fully consumed
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int e = tid + 256 * i;
-      xs[(e >> 6) * kXS + (e & 63)] = xr[i];
-      as[(e >> 6) * kAS + (e & 63)] = ar[i];
+    // next item of this workgroup: descriptors now, first chunk with the last chunk below
+    const int itn = it + stride;
+    const bool has_next = itn < end;
+    Seg sgn = sg;
+    int q0n = q0, Rcn = Rc;
+    if (has_next) {
+      sgn = segs[itn / nsl];
+      q0n = (itn % nsl) * RQ;
+      Rcn = min(R - q0n, RQ);
     }
-    __syncthreads();
-    int pn = p, kn = k0 + kKC;
-    Pair prn = pr;
-    if (kn >= pr.n) {
-      pn = p + 1;
-      kn = 0;
-      if (pn < sg.p1) prn = pairs[pn];
+    const Pair prn = pairs[sgn.p0];
+    floatx4 acc[NRI > 0 ? NRI * NCI : 1];
+#pragma unroll
+    for (int j = 0; j < (NRI > 0 ? NRI * NCI : 1); ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    int p = sg.p0, k0 = 0;
+    Pair pr1;  // descriptor of the tile's following pair, fetched one pair ahead
+    if (p + 1 < sg.p1) pr1 = pairs[p + 1];
+    while (true) {
+      __syncthreads();  // previous chunk fully consumed
+#pragma unroll
+      for (int i = 0; i < kXL; ++i) {
+        const int e = tid + kThreads * i;
+        const bool ok = (msk >> i) & 1u;
+        xs[(e >> 6) * kXS + (e & 63)] = make_float2(ok ? xr[i].x : 0.f, ok ? xr[i].y : 0.f);
+      }
+#pragma unroll
+      for (int i = 0; i < kAL; ++i) {
+        const int e = tid + kThreads * i;
+        const bool ok = (msk >> (kXL + i)) & 1u;
+        as[(e / kTileRows) * kAS + e % kTileRows] =
+            make_float2(ok ? ar[i].x * lscale : 0.f, ok ? ar[i].y * lscale : 0.f);
+      }
+      __syncthreads();
+      // the second half of a chunk past the pair's last column holds only zeros
+      const int nh = k0 + kKC / 2 < cur.n ? 2 : 1;
+      // the next chunk: same pair, next pair of the tile, or the next item's first
+      bool last = false, fetch = true;
+      if (k0 + kKC < cur.n) {
+        k0 += kKC;
+      } else if (p + 1 < sg.p1) {
+        ++p;
+        k0 = 0;
+        cur = chunk_src(pr1, R, q0, Rc, sg.m);
+        if (p + 1 < sg.p1) pr1 = pairs[p + 1];
+      } else {
+        last = true;
+        fetch = has_next;
+        k0 = 0;
+        cur = chunk_src(prn, R, q0n, Rcn, sgn.m);
+      }
+      if (fetch) {
+        msk = load_chunk<FT>(cur, k0, F, X, T, R, xr, ar);
+        lscale = cur.scale;
+      }
+      if (NRI > 0) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          if (h >= nh) break;
+          // this lane's two complex K rows of the half chunk: 8 h + 2 kk and 8 h + 2 kk + 1
+          float2 x0[NCI], x1[NCI];
+#pragma unroll
+          for (int ci = 0; ci < NCI; ++ci) {
+            x0[ci] = xl[8 * h * kXS + ci * CW * 8];
+            x1[ci] = xl[(8 * h + 1) * kXS + ci * CW * 8];
+          }
+          // row tiles in pairs when NCI = 1: every step interleaves at least two
+          // accumulators, so no MFMA waits on the one just issued
+          constexpr int JG = NCI == 1 && NRI > 1 ? 2 : 1;
+#pragma unroll
+          for (int j0 = 0; j0 < NRI; j0 += JG) {
+            float2 a0[JG], a1[JG];
+#pragma unroll
+            for (int u = 0; u < JG; ++u) {
+              const int j = j0 + u < NRI ? j0 + u : j0;
+              a0[u] = al[8 * h * kAS + j * RW * 16];
+              a1[u] = al[(8 * h + 1) * kAS + j * RW * 16];
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+#pragma unroll
+              for (int u = 0; u < JG; ++u) {
+                if (j0 + u < NRI) {
+                  const float2 a = t < 2 ? a0[u] : a1[u];
+                  const float av = (t & 1) ? a.y : a.x;
+#pragma unroll
+                  for (int ci = 0; ci < NCI; ++ci) {
+                    const float2 x = t < 2 ? x0[ci] : x1[ci];
+                    const float bv = (t & 1) ? (op ? x.x : -x.y) : (op ? x.y : x.x);
+                    const int j = (j0 + u) * NCI + ci;
+                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[j], 0, 0, 0);
+                  }
+                }
+              }
+            }
+          }
+        }
+      }
+      if (last) break;
     }
-    const bool has_next = pn < sg.p1;
-    if (has_next) HODBF_LOAD_CHUNK(prn, kn);  // in flight during the products below
-    if (NRI > 0) {
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int c0 = 8 * h + 2 * kk;  // this lane's two complex K rows of the half chunk
-        float2 x0[NCI], x1[NCI], a0[NRI > 0 ? NRI : 1], a1[NRI > 0 ? NRI : 1];
+    for (int ri = 0; ri < NRI; ++ri) {
+      const int rt = wr + ri * RW;
 #pragma unroll
-        for (int ci = 0; ci < NCI; ++ci) {
-          const int col = (wc + ci * cw) * 8 + qo;
-          x0[ci] = xs[c0 * kXS + col];
-          x1[ci] = xs[(c0 + 1) * kXS + col];
-        }
+      for (int v = 0; v < 4; ++v) {
+        const int row = rt * 16 + 4 * kk + v;
+        if (row < sg.m) {
+          const int64_t orow = mapped_row(rowmap, sg.map0, sg.map1, row);
 #pragma unroll
-        for (int ri = 0; ri < NRI; ++ri) {
-          const int rt = wr + ri * rw;
-          a0[ri] = as[c0 * kAS + rt * 16 + i16];
-          a1[ri] = as[(c0 + 1) * kAS + rt * 16 + i16];
-        }
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-#pragma unroll
-          for (int ri = 0; ri < NRI; ++ri) {
-            const float2 a = t < 2 ? a0[ri] : a1[ri];
-            const float av = (t & 1) ? a.y : a.x;
-#pragma unroll
-            for (int ci = 0; ci < NCI; ++ci) {
-              const float2 x = t < 2 ? x0[ci] : x1[ci];
-              const float bv = (t & 1) ? (op ? x.x : -x.y) : (op ? x.y : x.x);
-              acc[ri * NCI + ci] =
-                  __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[ri * NCI + ci], 0, 0, 0);
+          for (int ci = 0; ci < NCI; ++ci) {
+            const int q = q0 + (wc + ci * CW) * 8 + qo;
+            if (q < q0 + Rc) {
+              float *o = reinterpret_cast<float *>(OUT + orow * R + q) + op;
+              *o = beta ? *o + acc[ri * NCI + ci][v] : acc[ri * NCI + ci][v];
             }
           }
         }
       }
     }
     if (!has_next) break;
-    p = pn;
-    k0 = kn;
-    pr = prn;
-  }
-#undef HODBF_LOAD_CHUNK
-#pragma unroll
-  for (int ri = 0; ri < NRI; ++ri) {
-    const int rt = wr + ri * rw;
-#pragma unroll
-    for (int ci = 0; ci < NCI; ++ci) {
-      const int q = q0 + (wc + ci * cw) * 8 + qo;
-      if (q < q0 + Rc) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int row = rt * 16 + 4 * kk + v;
-          if (row < m) {
-            float *o = reinterpret_cast<float *>(OUT + int64_t(sg.out_row + row) * R + q) + op;
-            *o = beta ? *o + acc[ri * NCI + ci][v] : acc[ri * NCI + ci][v];
-          }
-        }
-      }
-    }
+    it = itn;
+    sg = sgn;
+    q0 = q0n;
+    Rc = Rcn;
   }
 }
 
+// Persistent grouped launch.  The tiles of a launch are sorted by their row-tile count
+// nrt (classes 1..kWaves); class c owns the workgroups [wg0[c], wg0[c + 1]) and the tiles
+// [seg0[c], seg0[c + 1]).  Within a class every wave has a fixed share of the tile's
+// 16 x 8 output tiles, so one loop instantiation serves all of its items; a narrower last
+// slice runs the full-slice instantiation (the extra column tiles read zeros and are not
+// stored).
+struct TileClasses {
+  int seg0[kWaves + 1];
+  int wg0[kWaves + 1];
+};
+
 template <typename FT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_grouped_mfma_f32(const Seg *__restrict__ segs,
-                                                          const Pair *__restrict__ pairs,
-                                                          const FT *__restrict__ F,
-                                                          const float2 *__restrict__ X,
-                                                          const float2 *__restrict__ T,
-                                                          float2 *__restrict__ OUT, int R,
-                                                          int beta, int RQ) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_grouped_mfma_f32(
+    const Seg *__restrict__ segs, const Pair *__restrict__ pairs, const RowMap *__restrict__ rowmap,
+    const FT *__restrict__ F, const float2 *__restrict__ X, const float2 *__restrict__ T,
+    float2 *__restrict__ OUT, int R, int beta, int RQ, int nsl, TileClasses tc) {
   __shared__ float2 xs[kKC * kXS];
   __shared__ float2 as[kKC * kAS];
-  const Seg sg = segs[blockIdx.x];
+  const int g = blockIdx.x;
+  int c = 0;
+  while (c < kWaves - 1 && g >= tc.wg0[c + 1]) ++c;
+  const int first = tc.seg0[c] * nsl + (g - tc.wg0[c]);
+  const int end = tc.seg0[c + 1] * nsl;
+  const int stride = tc.wg0[c + 1] - tc.wg0[c];
+  if (first >= end) return;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int nrt = (sg.m + 15) >> 4;
-  // blockIdx.y selects a slice of RQ (<= 64) right-hand sides; launches with few
-  // segments use narrow slices to put more workgroups on the chip
-  const int qend = min(R, int(blockIdx.y + 1) * RQ);
-  for (int q0 = blockIdx.y * RQ; q0 < qend; q0 += 64) {
-    const int Rc = qend - q0 < 64 ? qend - q0 : 64;
-    const int nnt = (Rc + 7) >> 3;
-    const int cw = nnt >= 4 ? 4 : (nnt >= 2 ? 2 : 1);  // wave columns
-    const int rw = 4 / cw;                             // wave rows
-    const int wc = wave % cw, wr = wave / cw;
-    // row tiles wr, wr + rw, ... below nrt; column tiles wc, wc + cw below nnt (<= 2)
-    const int nri = wr < nrt ? (nrt - wr + rw - 1) / rw : 0;
-    const int nci = wc < nnt ? (wc + cw < nnt ? 2 : 1) : 0;
-    const int sel = nci == 0 ? 0 : nri * 2 + (nci - 1);  // wave-uniform
-#define HODBF_CHUNKS(NR, NC)                                                                  \
-  grouped_chunks<FT, NR, NC>(sg, pairs, F, X, T, OUT, R, beta, q0, Rc, wr, rw, wc, cw, xs, as)
+  const int nrt = c + 1;
+  const int nnt = ((R < RQ ? R : RQ) + 7) >> 3;  // column tiles of a full slice
+  // the waves as a cw x rw grid: short tiles spread over column tiles, tall tiles
+  // over row tiles too; every wave then owns at most 4 row tiles x 2 column tiles
+  const int nntp = nnt >= 8 ? 8 : (nnt >= 4 ? 4 : (nnt >= 2 ? 2 : 1));
+  const int cw = (kWaves == 8 && nrt > 2) || nntp > kWaves ? (nntp > 4 ? 4 : nntp) : nntp;
+  const int rw = kWaves / cw;  // wave rows
+  const int wc = wave % cw, wr = wave / cw;
+  // row tiles wr, wr + rw, ... below nrt; column tiles wc, wc + cw below nnt (<= 2)
+  const int nri = wr < nrt ? (nrt - wr + rw - 1) / rw : 0;
+  const int nci = wc < nnt ? (wc + cw < nnt ? 2 : 1) : 0;
+  const int sel = nci == 0 ? 0 : nri * 2 + (nci - 1);  // wave-uniform
+#define HODBF_CLASS(NR, NC, RWV)                                                             \
+  class_items<FT, NR, NC, RWV>(first, end, stride, nsl, RQ, segs, pairs, rowmap, F, X, T, OUT, \
+                               R, beta, wr, wc, xs, as)
+  if (rw == 1) {
     switch (sel) {
-      case 2: HODBF_CHUNKS(1, 1); break;
-      case 3: HODBF_CHUNKS(1, 2); break;
-      case 4: HODBF_CHUNKS(2, 1); break;
-      case 5: HODBF_CHUNKS(2, 2); break;
-      case 6: HODBF_CHUNKS(3, 1); break;
-      case 7: HODBF_CHUNKS(3, 2); break;
-      case 8: HODBF_CHUNKS(4, 1); break;
-      case 9: HODBF_CHUNKS(4, 2); break;
-      default: HODBF_CHUNKS(0, 1); break;  // no tiles: loads and barriers only
+      case 2: HODBF_CLASS(1, 1, 1); break;
+      case 3: HODBF_CLASS(1, 2, 1); break;
+      case 4: HODBF_CLASS(2, 1, 1); break;
+      case 5: HODBF_CLASS(2, 2, 1); break;
+      case 6: HODBF_CLASS(3, 1, 1); break;
+      case 7: HODBF_CLASS(3, 2, 1); break;
+      case 8: HODBF_CLASS(4, 1, 1); break;
+      case 9: HODBF_CLASS(4, 2, 1); break;
+      default: HODBF_CLASS(0, 1, 1); break;  // no tiles: loads and barriers only
     }
-#undef HODBF_CHUNKS
-    __syncthreads();  // the next right-hand-side chunk reuses the LDS buffers
+  } else if (rw == 2) {
+    switch (sel) {
+      case 2: HODBF_CLASS(1, 1, 2); break;
+      case 3: HODBF_CLASS(1, 2, 2); break;
+      case 4: HODBF_CLASS(2, 1, 2); break;
+      case 5: HODBF_CLASS(2, 2, 2); break;
+      default: HODBF_CLASS(0, 1, 2); break;
+    }
+  } else {
+    if (sel == 2) HODBF_CLASS(1, 1, 4);
+    else HODBF_CLASS(0, 1, 4);
   }
+#undef HODBF_CLASS
 }
 
 // MFMA grouped GEMM, complex BF16 factors (v_mfma_f32_16x16x16bf16_1k): one MFMA
 // consumes 8 complex columns; lane slot kk holds real columns 4 kk .. 4 kk + 3, i.e.
 // (Re, Im) of complex columns 2 kk and 2 kk + 1.  Inputs are rounded to BF16 with
-// round-to-nearest-even; accumulation is FP32.
+// round-to-nearest-even; accumulation is FP32.  The tile is processed 64 rows at a time.
 __device__ inline short f_to_bf16(float f) {
   uint32_t u = __float_as_uint(f);
   u += 0x7FFFu + ((u >> 16) & 1u);
@@ -356,81 +504,85 @@ __device__ inline short f_to_bf16(float f) {
 
 __global__ __launch_bounds__(256) void k_grouped_mfma_bf16(const Seg *__restrict__ segs,
                                                            const Pair *__restrict__ pairs,
+                                                           const RowMap *__restrict__ rowmap,
                                                            const uint32_t *__restrict__ F,
                                                            const float2 *__restrict__ X,
                                                            const float2 *__restrict__ T,
                                                            float2 *__restrict__ OUT, int R,
                                                            int beta) {
   const Seg sg = segs[blockIdx.x];
-  const int m = sg.m;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nrt = (m + 15) >> 4;
-  const int nrtp = nrt == 3 ? 4 : nrt;
-  const int wpr = 4 / nrtp;
-  const int rt = wave / wpr;
-  if (rt >= nrt) return;
-  const int sub = wave % wpr;
-  const int ia = rt * 16 + (lane & 15);
   const int kk = lane >> 4;
   const int jc = lane & 15;
   const int qo = jc >> 1, op = jc & 1;
-  for (int q0 = 0; q0 < R; q0 += 64) {
-    const int Rc = R - q0 < 64 ? R - q0 : 64;
-    const int nnt = (Rc + 7) >> 3;
-    floatx4 acc[8];
+  for (int rb = 0; rb < sg.m; rb += 64) {
+    const int m = sg.m - rb < 64 ? sg.m - rb : 64;
+    const int nrt = (m + 15) >> 4;
+    const int nrtp = nrt == 3 ? 4 : nrt;
+    const int wpr = 4 / nrtp;
+    const int rt = wave / wpr;
+    if (rt >= nrt) continue;
+    const int sub = wave % wpr;
+    const int ia = rt * 16 + (lane & 15);
+    for (int q0 = 0; q0 < R; q0 += 64) {
+      const int Rc = R - q0 < 64 ? R - q0 : 64;
+      const int nnt = (Rc + 7) >> 3;
+      floatx4 acc[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    for (int p = sg.p0; p < sg.p1; ++p) {
-      const Pair pr = pairs[p];
-      const uint32_t *A = F + pr.f_off;
-      const float2 *in = (pr.in_buf ? T : X) + int64_t(pr.in_row) * R;
-      const int n = pr.n;
-      const float sc = pr.scale;  // applied to the inputs: the BF16 MFMA has no per-pair scale
-      for (int c0 = 0; c0 < n; c0 += 8) {
-        const int c = c0 + 2 * kk;
-        const bool rok = ia < m;
-        const uint32_t w0 = (rok && c < n) ? A[int64_t(c) * pr.lda + ia] : 0u;
-        const uint32_t w1 = (rok && c + 1 < n) ? A[int64_t(c + 1) * pr.lda + ia] : 0u;
-        shortx4 av;
-        av[0] = short(w0 & 0xFFFFu);
-        av[1] = short(w0 >> 16);
-        av[2] = short(w1 & 0xFFFFu);
-        av[3] = short(w1 >> 16);
-        const float2 z2 = make_float2(0.f, 0.f);
+      for (int j = 0; j < 8; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+      for (int p = sg.p0; p < sg.p1; ++p) {
+        const Pair pr = pairs[p];
+        const uint32_t *A = F + pr.f_off + rb;
+        const float2 *in = (pr.in_buf ? T : X) + int64_t(pr.in_row) * R;
+        const int n = pr.n;
+        const float sc = pr.scale;  // applied to the inputs: the BF16 MFMA has no per-pair scale
+        for (int c0 = 0; c0 < n; c0 += 8) {
+          const int c = c0 + 2 * kk;
+          const bool rok = ia < m;
+          const uint32_t w0 = (rok && c < n) ? A[int64_t(c) * pr.lda + ia] : 0u;
+          const uint32_t w1 = (rok && c + 1 < n) ? A[int64_t(c + 1) * pr.lda + ia] : 0u;
+          shortx4 av;
+          av[0] = short(w0 & 0xFFFFu);
+          av[1] = short(w0 >> 16);
+          av[2] = short(w1 & 0xFFFFu);
+          av[3] = short(w1 >> 16);
+          const float2 z2 = make_float2(0.f, 0.f);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const int nt = sub + j * wpr;
-          if (nt < nnt) {
-            const int q = q0 + nt * 8 + qo;
-            const bool qok = q < R;
-            float2 x0 = (qok && c < n) ? in[int64_t(c) * R + q] : z2;
-            float2 x1 = (qok && c + 1 < n) ? in[int64_t(c + 1) * R + q] : z2;
-            x0.x *= sc;
-            x0.y *= sc;
-            x1.x *= sc;
-            x1.y *= sc;
-            shortx4 bv;
-            bv[0] = f_to_bf16(op ? x0.y : x0.x);
-            bv[1] = f_to_bf16(op ? x0.x : -x0.y);
-            bv[2] = f_to_bf16(op ? x1.y : x1.x);
-            bv[3] = f_to_bf16(op ? x1.x : -x1.y);
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[j], 0, 0, 0);
+          for (int j = 0; j < 8; ++j) {
+            const int nt = sub + j * wpr;
+            if (nt < nnt) {
+              const int q = q0 + nt * 8 + qo;
+              const bool qok = q < R;
+              float2 x0 = (qok && c < n) ? in[int64_t(c) * R + q] : z2;
+              float2 x1 = (qok && c + 1 < n) ? in[int64_t(c + 1) * R + q] : z2;
+              x0.x *= sc;
+              x0.y *= sc;
+              x1.x *= sc;
+              x1.y *= sc;
+              shortx4 bv;
+              bv[0] = f_to_bf16(op ? x0.y : x0.x);
+              bv[1] = f_to_bf16(op ? x0.x : -x0.y);
+              bv[2] = f_to_bf16(op ? x1.y : x1.x);
+              bv[3] = f_to_bf16(op ? x1.x : -x1.y);
+              acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[j], 0, 0, 0);
+            }
           }
         }
       }
-    }
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int nt = sub + j * wpr;
-      if (nt < nnt) {
-        const int q = q0 + nt * 8 + qo;
-        if (q < R) {
+      for (int j = 0; j < 8; ++j) {
+        const int nt = sub + j * wpr;
+        if (nt < nnt) {
+          const int q = q0 + nt * 8 + qo;
+          if (q < R) {
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int row = rt * 16 + 4 * kk + v;
-            if (row < m) {
-              float *o = reinterpret_cast<float *>(OUT + int64_t(sg.out_row + row) * R + q) + op;
-              *o = beta ? *o + acc[j][v] : acc[j][v];
+            for (int v = 0; v < 4; ++v) {
+              const int row = rt * 16 + 4 * kk + v;
+              if (row < m) {
+                const int64_t orow = mapped_row(rowmap, sg.map0, sg.map1, rb + row);
+                float *o = reinterpret_cast<float *>(OUT + orow * R + q) + op;
+                *o = beta ? *o + acc[j][v] : acc[j][v];
+              }
             }
           }
         }
@@ -439,43 +591,71 @@ __global__ __launch_bounds__(256) void k_grouped_mfma_bf16(const Seg *__restrict
   }
 }
 
-void launch_grouped(const Seg *segs, const Pair *pairs, int64_t s0, int64_t ns, const void *F,
-                    int ftype, const float2 *X, const float2 *T, float2 *OUT, int R, int beta,
-                    hipStream_t st) {
+void launch_grouped(const Seg *segs, const Pair *pairs, const RowMap *rowmap, int64_t s0,
+                    int64_t ns, const int64_t *cls, const void *F, int ftype, const float2 *X,
+                    const float2 *T, float2 *OUT, int R, int beta, hipStream_t st) {
   if (ns <= 0 || R <= 0) return;
   const Seg *sp = segs + s0;
   if (R < 4) {
     const int64_t nb = (ns + 3) / 4;
     if (ftype == FT_C64)
       hipLaunchKernelGGL(k_grouped_gemv<float2>, dim3(unsigned(nb)), dim3(256), 0, st, sp, pairs,
-                         static_cast<const float2 *>(F), X, T, OUT, R, beta, ns);
+                         rowmap, static_cast<const float2 *>(F), X, T, OUT, R, beta, ns);
     else if (ftype == FT_BF16)
-      hipLaunchKernelGGL(k_grouped_gemv<FBF16>, dim3(unsigned(nb)), dim3(256), 0, st, sp,
-                         pairs, static_cast<const FBF16 *>(F), X, T, OUT, R, beta, ns);
+      hipLaunchKernelGGL(k_grouped_gemv<FBF16>, dim3(unsigned(nb)), dim3(256), 0, st, sp, pairs,
+                         rowmap, static_cast<const FBF16 *>(F), X, T, OUT, R, beta, ns);
     else
-      hipLaunchKernelGGL(k_grouped_gemv<FF16>, dim3(unsigned(nb)), dim3(256), 0, st, sp,
-                         pairs, static_cast<const FF16 *>(F), X, T, OUT, R, beta, ns);
+      hipLaunchKernelGGL(k_grouped_gemv<FF16>, dim3(unsigned(nb)), dim3(256), 0, st, sp, pairs,
+                         rowmap, static_cast<const FF16 *>(F), X, T, OUT, R, beta, ns);
     return;
   }
-  // right-hand-side slice per workgroup: 64, or narrower when a launch has too few
-  // segments to give every SIMD several waves
+  if (ftype == FT_BF16) {
+    hipLaunchKernelGGL(k_grouped_mfma_bf16, dim3(unsigned(ns)), dim3(256), 0, st, sp, pairs,
+                       rowmap, static_cast<const uint32_t *>(F), X, T, OUT, R, beta);
+    return;
+  }
+  // right-hand-side slice per work item: 64, or narrower when a launch has too few
+  // tiles to give every SIMD several waves
   static const int64_t min_wg = [] {
-    const char *e = std::getenv("HODBF_MIN_WORKGROUPS");  // tuning knob, default 1024
-    return e ? std::atoll(e) : int64_t(1024);
+    const char *e = std::getenv("HODBF_MIN_WORKGROUPS");  // tuning knob, default 512
+    return e ? std::atoll(e) : int64_t(512);
   }();
   int RQ = 64;
   while (RQ > 16 && ns * ((R + RQ - 1) / RQ) < min_wg) RQ >>= 1;
   if (RQ > R) RQ = R;
-  const dim3 grid(unsigned(ns), unsigned((R + RQ - 1) / RQ));
+  const int nsl = (R + RQ - 1) / RQ;
+  // cap on workgroups per launch (each then loops over several items); by default one
+  // workgroup per item, which measured faster than a resident-sized grid (the hardware
+  // dispatcher balances the uneven items)
+  static const int64_t resident = [] {
+    const char *e = std::getenv("HODBF_PERSIST_WORKGROUPS");  // tuning knob, 0 = no cap
+    return e ? int64_t(std::atoll(e)) : int64_t(0);
+  }();
+  // workgroups per class: one per item when the launch fits the resident set, else in
+  // proportion to the class's items (at least one per non-empty class)
+  int64_t items[kRowClasses];
+  for (int c = 0; c < kRowClasses; ++c) items[c] = (cls[c + 1] - cls[c]) * nsl;
+  const int64_t total = ns * nsl;
+  const bool fits = resident <= 0 || total <= resident;
+  TileClasses tc{};
+  int64_t acc = 0;
+  for (int c = 0; c < kRowClasses; ++c) {
+    tc.seg0[c] = int(cls[c]);
+    tc.wg0[c] = int(acc);
+    const int64_t g = fits || items[c] == 0
+                          ? items[c]
+                          : std::min(items[c], std::max<int64_t>(1, resident * items[c] / total));
+    acc += g;
+  }
+  tc.seg0[kRowClasses] = int(cls[kRowClasses]);
+  tc.wg0[kRowClasses] = int(acc);
+  const dim3 grid{unsigned(acc)};
   if (ftype == FT_C64)
-    hipLaunchKernelGGL(k_grouped_mfma_f32<float2>, grid, dim3(256), 0, st, sp, pairs,
-                       static_cast<const float2 *>(F), X, T, OUT, R, beta, RQ);
-  else if (ftype == FT_F16)
-    hipLaunchKernelGGL(k_grouped_mfma_f32<FF16>, grid, dim3(256), 0, st, sp, pairs,
-                       static_cast<const FF16 *>(F), X, T, OUT, R, beta, RQ);
+    hipLaunchKernelGGL(k_grouped_mfma_f32<float2>, grid, dim3(kThreads), 0, st, sp, pairs, rowmap,
+                       static_cast<const float2 *>(F), X, T, OUT, R, beta, RQ, nsl, tc);
   else
-    hipLaunchKernelGGL(k_grouped_mfma_bf16, dim3(unsigned(ns)), dim3(256), 0, st, sp, pairs,
-                       static_cast<const uint32_t *>(F), X, T, OUT, R, beta);
+    hipLaunchKernelGGL(k_grouped_mfma_f32<FF16>, grid, dim3(kThreads), 0, st, sp, pairs, rowmap,
+                       static_cast<const FF16 *>(F), X, T, OUT, R, beta, RQ, nsl, tc);
 }
 
 // ---------------------------------------------------------------------------

@@ -48,19 +48,22 @@ struct DevBuf {
 struct Launch {
   int64_t s0 = 0, ns = 0;
   int beta = 0, out = 0;
+  int64_t cls[kRowClasses + 1] = {};  // row-tile class boundaries (set at upload)
 };
 
 // A sequence of dependent grouped launches (one apply of a factor set).
 struct Program {
   std::vector<Launch> launches;
-  DevBuf segs, pairs;
+  DevBuf segs, pairs, rowmap;
   int64_t t_rows = 0;  // stage workspace rows
   int64_t nseg = 0, npair = 0;
 };
 
-// Host-side record of a stored block, for export and stats.
+// Host-side record of a stored block, for export and stats: element (i, k) of the
+// m x n block sits at off + k * lda + i of its arena (lda > m when blocks that share
+// an input are stacked).
 struct BlockRec {
-  int64_t kind, l, i, ca, cb, lev, a, b, m, n, off;
+  int64_t kind, l, i, ca, cb, lev, a, b, m, n, off, lda;
 };
 
 struct PrecondLevel {

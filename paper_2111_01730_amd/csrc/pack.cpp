@@ -1,6 +1,13 @@
 // Packing of butterfly factors into device programs: stage-by-stage grouped launches
 // (all butterflies of a set advance one level per launch) and a final per-leaf reduce
 // that applies the outer factors B^L (and the dense leaf blocks for Z_con).
+//
+// Blocks that read the same input rows are stacked into one matrix so the input is
+// streamed once: at the first stage every V^0 block whose column leaf is nu (one per
+// butterfly level), at later stages the two transfer blocks W_{tau1,nu} and
+// W_{tau2,nu} of sibling row clusters, whose input is the same [t(p,nu1); t(p,nu2)].
+// Each stacked matrix is cut into balanced tiles of at most kTileRows rows whose row
+// maps scatter the rows back to each block's own output range.
 #include <algorithm>
 #include <functional>
 
@@ -9,26 +16,71 @@
 namespace hodbf {
 
 namespace {
-constexpr int kTile = 64;  // output rows per segment (4 MFMA row tiles)
-}
 
+struct Member {
+  const Mat *f;
+  int64_t out_row;
+  int64_t kind, md[4], s, a, b;
+};
 
-
-static void add_seg(PackSink &pk, int64_t out_row, int64_t m, const std::vector<Pair> &prs) {
-  // prs all share m rows; split rows into tiles of kTile
-  for (int64_t i0 = 0; i0 < m; i0 += kTile) {
-    Seg s;
-    s.out_row = int32_t(out_row + i0);
-    s.m = int32_t(std::min<int64_t>(kTile, m - i0));
-    s.p0 = int32_t(pk.pairs.size());
-    for (Pair p : prs) {
-      p.f_off += i0;
-      pk.pairs.push_back(p);
+// Stack the members (same n) into one column-major matrix and emit its tiles.
+void emit_group(PackSink &pk, const std::vector<Member> &mem, int32_t in_buf, int64_t in_row,
+                int64_t n) {
+  int64_t mt = 0;
+  for (auto &m : mem) mt += m.f->m;
+  if (mt == 0 || n == 0) return;
+  Mat S;
+  S.m = int(mt);
+  S.n = int(n);
+  S.v.resize(size_t(mt) * size_t(n));
+  std::vector<int64_t> roff;
+  int64_t r = 0;
+  for (auto &m : mem) {
+    roff.push_back(r);
+    for (int64_t k = 0; k < n; ++k)
+      for (int64_t i = 0; i < m.f->m; ++i)
+        S.v[size_t(k * mt + r + i)] = m.f->v[size_t(k * m.f->m + i)];
+    r += m.f->m;
+  }
+  float scale = 1.0f;
+  const int64_t f_off = pk.put_host(S, &scale);
+  for (size_t j = 0; j < mem.size(); ++j) {
+    const Member &m = mem[j];
+    if (m.f->m == 0) continue;
+    pk.table->push_back({m.kind, m.md[0], m.md[1], m.md[2], m.md[3], m.s, m.a, m.b, m.f->m, n,
+                         f_off + roff[j], mt});
+    if (pk.scales) pk.scales->push_back(scale);
+  }
+  // balanced tiles whose row counts are multiples of the 16-row MFMA tile (but the last)
+  const int64_t ntile = (mt + kTileRows - 1) / kTileRows;
+  const int64_t per = ((mt + 15) / 16 + ntile - 1) / ntile * 16;
+  for (int64_t r0 = 0; r0 < mt; r0 += per) {
+    const int64_t r1 = std::min(mt, r0 + per);
+    Seg sg{};
+    sg.m = int32_t(r1 - r0);
+    sg.p0 = int32_t(pk.pairs.size());
+    Pair p{};
+    p.f_off = f_off + r0;
+    p.in_row = int32_t(in_row);
+    p.n = int32_t(n);
+    p.lda = int32_t(mt);
+    p.in_buf = in_buf;
+    p.scale = scale;
+    pk.pairs.push_back(p);
+    sg.p1 = int32_t(pk.pairs.size());
+    sg.map0 = int32_t(pk.rowmap.size());
+    for (size_t j = 0; j < mem.size(); ++j) {
+      const int64_t a0 = roff[j], a1 = roff[j] + mem[j].f->m;
+      if (a1 <= r0 || a0 >= r1) continue;
+      const int64_t st = std::max(a0, r0);
+      pk.rowmap.push_back({int32_t(st - r0), int32_t(mem[j].out_row + (st - a0))});
     }
-    s.p1 = int32_t(pk.pairs.size());
-    pk.segs.push_back(s);
+    sg.map1 = int32_t(pk.rowmap.size());
+    pk.segs.push_back(sg);
   }
 }
+
+}  // namespace
 
 // Pack one set of butterflies whose row and column trees end at the leaves of T_H.
 // meta(bf) gives (l, i, ca, cb) for the block table.
@@ -41,46 +93,70 @@ void pack_group(PackSink &pk, const Tree &t, const std::vector<const Butterfly *
   // off[k][s][idx]: first workspace row of output (a, b) at stage s of butterfly k
   std::vector<std::vector<std::vector<int64_t>>> off(bfs.size());
   for (size_t k = 0; k < bfs.size(); ++k) off[k].resize(bfs[k]->L + 1);
+  const int64_t nleaf = int64_t(1) << LH;
   for (int s = 0; s <= Lmax; ++s) {
     const int64_t seg0 = int64_t(pk.segs.size());
+    // workspace rows of this stage: butterfly-major, then a-major, b-minor
     for (size_t k = 0; k < bfs.size(); ++k) {
       const Butterfly &bf = *bfs[k];
       if (bf.L < s) continue;
       const int64_t na = int64_t(1) << s, nb = int64_t(1) << (bf.L - s);
-      int64_t md[4];
-      meta(bf, md);
-      off[k][s].resize(static_cast<size_t>(na * nb));
-      for (int64_t a = 0; a < na; ++a)
-        for (int64_t b = 0; b < nb; ++b) {
-          const Mat &f = s == 0 ? bf.V0[size_t(b)] : bf.W[s][size_t(a * nb + b)];
-          const int64_t out_row = pk.t_rows;
-          off[k][s][size_t(a * nb + b)] = out_row;
-          pk.t_rows += f.m;
+      off[k][s].resize(size_t(na * nb));
+      for (int64_t e = 0; e < na * nb; ++e) {
+        const Mat &f = s == 0 ? bf.V0[size_t(e)] : bf.W[s][size_t(e)];
+        off[k][s][size_t(e)] = pk.t_rows;
+        pk.t_rows += f.m;
+      }
+    }
+    if (s == 0) {
+      // group V^0 blocks by their input leaf
+      std::vector<std::vector<Member>> byleaf(static_cast<size_t>(nleaf));
+      for (size_t k = 0; k < bfs.size(); ++k) {
+        const Butterfly &bf = *bfs[k];
+        int64_t md[4];
+        meta(bf, md);
+        for (int64_t b = 0; b < (int64_t(1) << bf.L); ++b) {
+          const Mat &f = bf.V0[size_t(b)];
           if (f.m == 0 || f.n == 0) continue;
-          Pair p{};
-          p.lda = f.m;
-          p.n = f.n;
-          if (s == 0) {
-            const int64_t nu = (bf.si << bf.L) + b;
-            p.in_buf = 0;
-            p.in_row = t.node_lo(LH, nu);
-          } else {
-            p.in_buf = 1;
-            p.in_row = int32_t(off[k][s - 1][size_t((a / 2) * 2 * nb + 2 * b)]);
-          }
-          p.f_off = pk.put_host(f, &p.scale);
-          pk.table->push_back({s == 0 ? 1 : 2, md[0], md[1], md[2], md[3], s, a, b, f.m, f.n,
-                               p.f_off});
-          if (pk.scales) pk.scales->push_back(p.scale);
-          add_seg(pk, out_row, f.m, {p});
+          const int64_t nu = (bf.si << bf.L) + b;
+          byleaf[size_t(nu)].push_back(
+              {&f, off[k][0][size_t(b)], 1, {md[0], md[1], md[2], md[3]}, 0, 0, b});
         }
+      }
+      for (int64_t nu = 0; nu < nleaf; ++nu)
+        if (!byleaf[size_t(nu)].empty())
+          emit_group(pk, byleaf[size_t(nu)], 0, t.node_lo(LH, nu),
+                     t.node_hi(LH, nu) - t.node_lo(LH, nu));
+    } else {
+      // group the two sibling transfer blocks that read the same input segment
+      for (size_t k = 0; k < bfs.size(); ++k) {
+        const Butterfly &bf = *bfs[k];
+        if (bf.L < s) continue;
+        int64_t md[4];
+        meta(bf, md);
+        const int64_t nb = int64_t(1) << (bf.L - s);
+        for (int64_t ap = 0; ap < (int64_t(1) << (s - 1)); ++ap)
+          for (int64_t b = 0; b < nb; ++b) {
+            std::vector<Member> mem;
+            int64_t n = 0;
+            for (int c = 0; c < 2; ++c) {
+              const int64_t a = 2 * ap + c;
+              const Mat &f = bf.W[s][size_t(a * nb + b)];
+              n = f.n;
+              if (f.m == 0 || f.n == 0) continue;
+              mem.push_back(
+                  {&f, off[k][s][size_t(a * nb + b)], 2, {md[0], md[1], md[2], md[3]}, s, a, b});
+            }
+            if (!mem.empty())
+              emit_group(pk, mem, 1, off[k][s - 1][size_t(ap * 2 * nb + 2 * b)], n);
+          }
+      }
     }
     const int64_t ns = int64_t(pk.segs.size()) - seg0;
     if (ns > 0) pk.launches.push_back({seg0, ns, 0, 0});
   }
   // final reduce: every leaf g gets its dense block (forward) and one outer block B_a
   // from each butterfly whose row tree holds g
-  const int64_t nleaf = int64_t(1) << LH;
   std::vector<std::vector<std::pair<int, int64_t>>> cover(static_cast<size_t>(nleaf));
   for (size_t k = 0; k < bfs.size(); ++k) {
     const Butterfly &bf = *bfs[k];
@@ -91,7 +167,9 @@ void pack_group(PackSink &pk, const Tree &t, const std::vector<const Butterfly *
   for (int64_t g = 0; g < nleaf; ++g) {
     const int32_t lo = t.node_lo(LH, g), hi = t.node_hi(LH, g);
     const int64_t m = hi - lo;
-    std::vector<Pair> prs;
+    Seg sg{};
+    sg.m = int32_t(m);
+    sg.p0 = int32_t(pk.pairs.size());
     if (forward) {
       Pair p{};
       p.scale = 1.0f;
@@ -102,9 +180,9 @@ void pack_group(PackSink &pk, const Tree &t, const std::vector<const Butterfly *
       p.lda = int32_t(m);
       pk.jobs->push_back({p.f_off, lo, int32_t(m), int32_t(pk.jobcols->size()), int32_t(m)});
       for (int32_t c = lo; c < hi; ++c) pk.jobcols->push_back(c);
-      pk.table->push_back({0, LH, g, 0, 0, 0, 0, 0, m, m, p.f_off});
+      pk.table->push_back({0, LH, g, 0, 0, 0, 0, 0, m, m, p.f_off, m});
       if (pk.scales) pk.scales->push_back(1.0f);
-      prs.push_back(p);
+      pk.pairs.push_back(p);
     }
     for (auto [k, a] : cover[size_t(g)]) {
       const Butterfly &bf = *bfs[size_t(k)];
@@ -127,23 +205,40 @@ void pack_group(PackSink &pk, const Tree &t, const std::vector<const Butterfly *
       } else {
         p.f_off = pk.put_host(bf.B[size_t(a)], &p.scale);
       }
-      pk.table->push_back({3, md[0], md[1], md[2], md[3], bf.L, a, 0, m, r, p.f_off});
+      pk.table->push_back({3, md[0], md[1], md[2], md[3], bf.L, a, 0, m, r, p.f_off, m});
       if (pk.scales) pk.scales->push_back(p.scale);
-      prs.push_back(p);
+      pk.pairs.push_back(p);
     }
-    if (!prs.empty()) add_seg(pk, lo, m, prs);
+    sg.p1 = int32_t(pk.pairs.size());
+    if (sg.p1 > sg.p0) {
+      sg.map0 = int32_t(pk.rowmap.size());
+      pk.rowmap.push_back({0, lo});
+      sg.map1 = int32_t(pk.rowmap.size());
+      pk.segs.push_back(sg);
+    }
   }
   const int64_t ns = int64_t(pk.segs.size()) - seg0;
   if (ns > 0) pk.launches.push_back({seg0, ns, final_beta, 1});
 }
 
 void upload_program(Program &prog, PackSink &pk, hipStream_t st) {
+  // sort each launch's segments by row-tile count (their order within a launch is free:
+  // they write disjoint rows) and record the class boundaries
+  for (Launch &ln : pk.launches) {
+    auto b = pk.segs.begin() + ln.s0, e = b + ln.ns;
+    auto nrt = [](const Seg &sg) { return std::min(kRowClasses, std::max(1, (sg.m + 15) / 16)); };
+    std::stable_sort(b, e, [&](const Seg &x, const Seg &y) { return nrt(x) < nrt(y); });
+    for (int c = 0; c <= kRowClasses; ++c)
+      ln.cls[c] = std::lower_bound(b, e, c + 1, [&](const Seg &sg, int v) { return nrt(sg) < v; }) - b;
+  }
   prog.launches = pk.launches;
   prog.t_rows = pk.t_rows;
   prog.nseg = int64_t(pk.segs.size());
   prog.npair = int64_t(pk.pairs.size());
   if (prog.nseg) prog.segs.upload(pk.segs.data(), pk.segs.size() * sizeof(Seg), st);
   if (prog.npair) prog.pairs.upload(pk.pairs.data(), pk.pairs.size() * sizeof(Pair), st);
+  if (!pk.rowmap.empty())
+    prog.rowmap.upload(pk.rowmap.data(), pk.rowmap.size() * sizeof(RowMap), st);
 }
 
 }  // namespace hodbf

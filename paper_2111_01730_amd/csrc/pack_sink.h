@@ -11,6 +11,7 @@ namespace hodbf {
 struct PackSink {
   std::vector<Seg> segs;
   std::vector<Pair> pairs;
+  std::vector<RowMap> rowmap;
   std::vector<Launch> launches;
   int64_t t_rows = 0;
   std::vector<BlockRec> *table = nullptr;

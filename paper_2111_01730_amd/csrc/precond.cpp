@@ -218,11 +218,17 @@ void build_precond(hodbf_op &op, hipStream_t st) {
       pr.n = m;
       pr.lda = m;
       pr.in_buf = 0;
-      pk.table->push_back({0, LH, g, 0, 0, 0, 0, 0, m, m, pr.f_off});
+      pk.table->push_back({0, LH, g, 0, 0, 0, 0, 0, m, m, pr.f_off, m});
       pd.scales.push_back(pr.scale);
-      Seg s{lo, m, int32_t(pk.pairs.size()), int32_t(pk.pairs.size() + 1)};
+      Seg sg{};
+      sg.m = m;
+      sg.p0 = int32_t(pk.pairs.size());
+      sg.p1 = sg.p0 + 1;
+      sg.map0 = int32_t(pk.rowmap.size());
+      sg.map1 = sg.map0 + 1;
+      pk.rowmap.push_back({0, lo});
       pk.pairs.push_back(pr);
-      pk.segs.push_back(s);
+      pk.segs.push_back(sg);
     }
     pk.launches.push_back({0, int64_t(pk.segs.size()), 0, 1});
     upload_program(pd.leaf, pk, st);

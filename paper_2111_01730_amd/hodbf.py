@@ -134,12 +134,12 @@ class Operator:
         return self.export(0, np.int32)
 
     def forward_blocks(self):
-        """(table as int64 (k, 11), values complex64) of the forward operator."""
-        return self.export(1, np.int64).reshape(-1, 11), self.export(2, np.complex64)
+        """(table as int64 (k, 12), values complex64) of the forward operator."""
+        return self.export(1, np.int64).reshape(-1, 12), self.export(2, np.complex64)
 
     def precond_blocks(self, copy="fp32"):
         vals = self.export({"fp32": 4, "bf16": 5, "fp16": 6}[copy], np.complex64)
-        return self.export(3, np.int64).reshape(-1, 11), vals
+        return self.export(3, np.int64).reshape(-1, 12), vals
 
 
 __all__ = ["Operator", "P_NONE", "P_FP32", "P_BF16", "P_BOTH", "P_FP16"]

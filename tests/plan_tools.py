@@ -23,8 +23,10 @@ def tree_from_perm(perm, n, depth):
     return Tree(np.asarray(perm, dtype=np.int64), ranges)
 
 
-def _mat(vals, off, m, n):
-    return np.asarray(vals[off:off + m * n], dtype=np.complex128).reshape(n, m).T
+def _mat(vals, off, m, n, lda=None):
+    lda = m if not lda else lda
+    cols = [np.asarray(vals[off + k * lda: off + k * lda + m], dtype=np.complex128) for k in range(n)]
+    return np.stack(cols, axis=1) if n else np.zeros((m, 0), dtype=np.complex128)
 
 
 def butterflies_from_table(tree, table, vals, skel=None, grid=None, precond=False):
@@ -32,10 +34,10 @@ def butterflies_from_table(tree, table, vals, skel=None, grid=None, precond=Fals
     LH = tree.depth
     groups = {}
     for row in table:
-        kind, l, i, ca, cb, lev, a, b, m, n, off = (int(v) for v in row)
+        kind, l, i, ca, cb, lev, a, b, m, n, off, lda = (int(v) for v in row)
         if kind == 0:
             continue
-        groups.setdefault((l, i, ca, cb), []).append((kind, lev, a, b, m, n, off))
+        groups.setdefault((l, i, ca, cb), []).append((kind, lev, a, b, m, n, off, lda))
     out = {}
     perm = tree.perm
     for (l, i, ca, cb), rows in groups.items():
@@ -50,18 +52,18 @@ def butterflies_from_table(tree, table, vals, skel=None, grid=None, precond=Fals
         W = [None] + [[[None] * (1 << (L - lv)) for _ in range(1 << lv)] for lv in range(1, L + 1)]
         B = [None] * (1 << L)
         # zero-rank factors are absent from device tables: default to empty matrices
-        for kind, lev, a, b, m, n, off in rows:
+        for kind, lev, a, b, m, n, off, lda in rows:
             if kind == 1:
-                V0[b] = _mat(vals, off, m, n)
+                V0[b] = _mat(vals, off, m, n, lda)
             elif kind == 2:
-                W[lev][a][b] = _mat(vals, off, m, n)
+                W[lev][a][b] = _mat(vals, off, m, n, lda)
             elif kind == 3:
                 if skel is not None:
                     cols = skel[off:off + n]
                     lo, hi = rr[a]
                     B[a] = vie.entries(grid, perm[np.arange(lo, hi)], perm[cols])
                 else:
-                    B[a] = _mat(vals, off, m, n)
+                    B[a] = _mat(vals, off, m, n, lda)
         out[(l, i, ca, cb)] = (L, rr, cr, V0, W, B)
     return out
 
@@ -101,7 +103,7 @@ def hodbf_from_export(grid, perm, table, vals, skel=None):
         D = [None] * (1 << LH)
         for row in table:
             if int(row[0]) == 0:
-                D[int(row[2])] = _mat(vals, int(row[10]), int(row[8]), int(row[9]))
+                D[int(row[2])] = _mat(vals, int(row[10]), int(row[8]), int(row[9]), int(row[11]))
     else:
         D = [vie.entries(grid, tree.perm[lo:hi], tree.perm[lo:hi]) for lo, hi in tree.ranges[LH]]
     groups = butterflies_from_table(tree, table, vals, skel, grid)
@@ -126,7 +128,7 @@ def precond_from_export(grid, perm, table, vals, depth):
     Dinv = [None] * (1 << LH)
     for row in table:
         if int(row[0]) == 0:
-            Dinv[int(row[2])] = _mat(vals, int(row[10]), int(row[8]), int(row[9]))
+            Dinv[int(row[2])] = _mat(vals, int(row[10]), int(row[8]), int(row[9]), int(row[11]))
     groups = butterflies_from_table(tree, table, vals, precond=True)
     X = {}
     levels = sorted({k[0] for k in groups})

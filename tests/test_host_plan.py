@@ -32,7 +32,7 @@ def test_every_declared_symbol_is_exported():
 def _probe_all(grid, tol, seed=1):
     p = _lib.make_params(grid, tol, seed=seed)
     perm = _lib.probe(p, 0, np.int32)
-    table = _lib.probe(p, 1, np.int64).reshape(-1, 11)
+    table = _lib.probe(p, 1, np.int64).reshape(-1, 12)
     vals = _lib.probe(p, 2, np.float64).view(np.complex128)
     skel = _lib.probe(p, 6, np.int32)
     return perm, table, vals, skel
