@@ -20,6 +20,7 @@ struct RowMap {
 };
 constexpr int kTileRows = 64;  // rows of one workgroup tile; leaves hold at most 64 rows
 constexpr int kRowClasses = kTileRows / 16;  // tiles of 1..kRowClasses 16-row MFMA tiles
+constexpr int kMaxMapEntries = 8;  // row map entries of one tile (the array is padded by as many)
 
 // A factor block (column-major, element (i, k) at f_off + k * lda + i, stored values
 // multiplied by scale on load) times the input rows [in_row, in_row + n) of buffer X

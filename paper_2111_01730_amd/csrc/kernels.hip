@@ -397,20 +397,40 @@ __device__ __forceinline__ void class_items(int it, const int end, const int str
       }
       if (last) break;
     }
+    {
+      // the tile's row map (at most kMaxMapEntries entries, read with uniform loads;
+      // the array is padded past its end) resolved per row in registers; accumulation
+      // into the output is a non-returning atomic add (each output element belongs to
+      // exactly one item, so it is a plain read-modify-write with nothing to wait on)
+      const int ne = sg.map1 - sg.map0;
+      int mstart[kMaxMapEntries], mbase[kMaxMapEntries];
 #pragma unroll
-    for (int ri = 0; ri < NRI; ++ri) {
-      const int rt = wr + ri * RW;
+      for (int k = 0; k < kMaxMapEntries; ++k) {
+        const RowMap e = rowmap[sg.map0 + k];
+        mstart[k] = k < ne ? e.start : kTileRows;
+        mbase[k] = e.out_row - e.start;
+      }
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = rt * 16 + 4 * kk + v;
-        if (row < sg.m) {
-          const int64_t orow = mapped_row(rowmap, sg.map0, sg.map1, row);
+      for (int ri = 0; ri < NRI; ++ri) {
+        const int rt = wr + ri * RW;
 #pragma unroll
-          for (int ci = 0; ci < NCI; ++ci) {
-            const int q = q0 + (wc + ci * CW) * 8 + qo;
-            if (q < q0 + Rc) {
-              float *o = reinterpret_cast<float *>(OUT + orow * R + q) + op;
-              *o = beta ? *o + acc[ri * NCI + ci][v] : acc[ri * NCI + ci][v];
+        for (int v = 0; v < 4; ++v) {
+          const int row = rt * 16 + 4 * kk + v;
+          int base = mbase[0];
+#pragma unroll
+          for (int k = 1; k < kMaxMapEntries; ++k) base = mstart[k] <= row ? mbase[k] : base;
+          if (row < sg.m) {
+            const int64_t orow = int64_t(base) + row;
+#pragma unroll
+            for (int ci = 0; ci < NCI; ++ci) {
+              const int q = q0 + (wc + ci * CW) * 8 + qo;
+              if (q < q0 + Rc) {
+                float *o = reinterpret_cast<float *>(OUT + orow * R + q) + op;
+                if (beta)
+                  unsafeAtomicAdd(o, acc[ri * NCI + ci][v]);
+                else
+                  *o = acc[ri * NCI + ci][v];
+              }
             }
           }
         }

@@ -51,11 +51,21 @@ void emit_group(PackSink &pk, const std::vector<Member> &mem, int32_t in_buf, in
                          f_off + roff[j], mt});
     if (pk.scales) pk.scales->push_back(scale);
   }
-  // balanced tiles whose row counts are multiples of the 16-row MFMA tile (but the last)
+  // balanced tiles whose row counts are multiples of the 16-row MFMA tile (but the last),
+  // cut early where a tile would span more than kMaxMapEntries blocks
   const int64_t ntile = (mt + kTileRows - 1) / kTileRows;
   const int64_t per = ((mt + 15) / 16 + ntile - 1) / ntile * 16;
-  for (int64_t r0 = 0; r0 < mt; r0 += per) {
-    const int64_t r1 = std::min(mt, r0 + per);
+  for (int64_t r0 = 0, r1 = 0; r0 < mt; r0 = r1) {
+    r1 = std::min(mt, r0 + per);
+    int spanned = 0;
+    for (size_t j = 0; j < mem.size(); ++j) {
+      const int64_t a0 = roff[j], a1 = roff[j] + mem[j].f->m;
+      if (a1 <= r0 || a0 >= r1) continue;
+      if (++spanned > kMaxMapEntries) {
+        r1 = a0;
+        break;
+      }
+    }
     Seg sg{};
     sg.m = int32_t(r1 - r0);
     sg.p0 = int32_t(pk.pairs.size());
@@ -237,8 +247,9 @@ void upload_program(Program &prog, PackSink &pk, hipStream_t st) {
   prog.npair = int64_t(pk.pairs.size());
   if (prog.nseg) prog.segs.upload(pk.segs.data(), pk.segs.size() * sizeof(Seg), st);
   if (prog.npair) prog.pairs.upload(pk.pairs.data(), pk.pairs.size() * sizeof(Pair), st);
-  if (!pk.rowmap.empty())
-    prog.rowmap.upload(pk.rowmap.data(), pk.rowmap.size() * sizeof(RowMap), st);
+  // padded so a tile's kMaxMapEntries uniform reads stay inside the array
+  pk.rowmap.resize(pk.rowmap.size() + kMaxMapEntries, RowMap{0, 0});
+  prog.rowmap.upload(pk.rowmap.data(), pk.rowmap.size() * sizeof(RowMap), st);
 }
 
 }  // namespace hodbf
