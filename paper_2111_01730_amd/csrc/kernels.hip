@@ -444,6 +444,17 @@ __device__ __forceinline__ void class_items(int it, const int end, const int str
   }
 }
 
+// Work index of this workgroup.  Blocks are dealt to the kNumXcd XCDs round-robin; here
+// groups of kXcdGroup consecutive work indices are dealt instead (group j to XCD j mod
+// kNumXcd, its members in consecutive slots of that XCD), so neighbouring tiles, which
+// often read the same input rows, share an L2 while the load stays balanced.  gridDim.x
+// is a multiple of kNumXcd * kXcdGroup.
+constexpr int kNumXcd = 8, kXcdGroup = 8;
+__device__ __forceinline__ int xcd_work_index() {
+  const int x = int(blockIdx.x % kNumXcd), l = int(blockIdx.x / kNumXcd);
+  return ((l / kXcdGroup) * kNumXcd + x) * kXcdGroup + l % kXcdGroup;
+}
+
 // Persistent grouped launch.  The tiles of a launch are sorted by their row-tile count
 // nrt (classes 1..kWaves); class c owns the workgroups [wg0[c], wg0[c + 1]) and the tiles
 // [seg0[c], seg0[c + 1]).  Within a class every wave has a fixed share of the tile's
@@ -462,7 +473,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
     float2 *__restrict__ OUT, int R, int beta, int RQ, int nsl, TileClasses tc) {
   __shared__ float2 xs[kKC * kXS];
   __shared__ float2 as[kKC * kAS];
-  const int g = blockIdx.x;
+  // neighbouring work on one XCD (see xcd_work_index); the padded grid's extra blocks exit
+  const int g = xcd_work_index();
+  if (g >= tc.wg0[kWaves]) return;
   int c = 0;
   while (c < kWaves - 1 && g >= tc.wg0[c + 1]) ++c;
   const int first = tc.seg0[c] * nsl + (g - tc.wg0[c]);
@@ -669,7 +682,8 @@ void launch_grouped(const Seg *segs, const Pair *pairs, const RowMap *rowmap, in
   }
   tc.seg0[kRowClasses] = int(cls[kRowClasses]);
   tc.wg0[kRowClasses] = int(acc);
-  const dim3 grid{unsigned(acc)};
+  constexpr int64_t gq = kNumXcd * kXcdGroup;
+  const dim3 grid{unsigned((acc + gq - 1) / gq * gq)};
   if (ftype == FT_C64)
     hipLaunchKernelGGL(k_grouped_mfma_f32<float2>, grid, dim3(kThreads), 0, st, sp, pairs, rowmap,
                        static_cast<const float2 *>(F), X, T, OUT, R, beta, RQ, nsl, tc);

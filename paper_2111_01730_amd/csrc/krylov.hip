@@ -98,27 +98,47 @@ void launch_multidot(const double2 *V, int64_t vstride, int nv, const double2 *w
                      partial);
 }
 
-__global__ void k_reduce_partials(const double2 *__restrict__ partial, int nblk, int nv, int R,
-                                  double2 *__restrict__ out, int accumulate) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nv * R) return;
+// out[e] (+)= sum over the nblk block partials of element e (e < nv * R).  A workgroup
+// owns 16 consecutive elements; its 16 thread groups sum interleaved partials
+// (b = g, g + 16, ...) and the 16 group sums are added in group order, so the result
+// does not depend on scheduling.
+__global__ __launch_bounds__(256) void k_reduce_partials(const double2 *__restrict__ partial,
+                                                         int nblk, int nv, int R,
+                                                         double2 *__restrict__ out,
+                                                         int accumulate) {
+  __shared__ double2 red[16][17];
+  const int tot = nv * R;
+  const int el = threadIdx.x & 15, g = threadIdx.x >> 4;
+  const int e = blockIdx.x * 16 + el;
   double2 s = make_double2(0.0, 0.0);
-  for (int b = 0; b < nblk; ++b) {
-    const double2 p = partial[int64_t(b) * nv * R + e];
-    s.x += p.x;
-    s.y += p.y;
+  if (e < tot) {
+#pragma unroll 4
+    for (int b = g; b < nblk; b += 16) {
+      const double2 p = partial[int64_t(b) * tot + e];
+      s.x += p.x;
+      s.y += p.y;
+    }
   }
-  if (accumulate) {
-    s.x += out[e].x;
-    s.y += out[e].y;
+  red[g][el] = s;
+  __syncthreads();
+  if (g == 0 && e < tot) {
+    double2 t = red[0][el];
+    for (int k = 1; k < 16; ++k) {
+      t.x += red[k][el].x;
+      t.y += red[k][el].y;
+    }
+    if (accumulate) {
+      t.x += out[e].x;
+      t.y += out[e].y;
+    }
+    out[e] = t;
   }
-  out[e] = s;
 }
 
 void launch_reduce_partials(const double2 *partial, int nblk, int nv, int R, double2 *out,
                             int accumulate, hipStream_t st) {
   const int tot = nv * R;
-  hipLaunchKernelGGL(k_reduce_partials, dim3((tot + 127) / 128), dim3(128), 0, st, partial, nblk,
+  hipLaunchKernelGGL(k_reduce_partials, dim3((tot + 15) / 16), dim3(256), 0, st, partial, nblk,
                      nv, R, out, accumulate);
 }
 
