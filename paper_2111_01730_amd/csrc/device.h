@@ -87,6 +87,14 @@ void launch_xupdate(const float2 *Zs, int64_t zstride, int nv, const double2 *y,
                     int64_t n, int R, hipStream_t st);
 // out = a - b
 void launch_axpby(const double2 *a, const double2 *b, double2 *out, int64_t count, hipStream_t st);
+// Column selection on [rows][R]-layout blocks: gather dst[r][k] = src[r][idx[k]] (k < Rd),
+// scatter dst[r][idx[k]] = src[r][k] (k < Rs).
+template <typename T>
+void launch_gather_cols(const T *src, int64_t rows, int Rs, const int32_t *idx, int Rd, T *dst,
+                        hipStream_t st);
+template <typename T>
+void launch_scatter_cols(const T *src, int64_t rows, int Rs, const int32_t *idx, int Rd, T *dst,
+                         hipStream_t st);
 
 // Per-column GMRES bookkeeping on the device.  H is stored column by column: column j
 // at H + j * (m + 1) * R, entry (i, q) at i * R + q.

@@ -4,6 +4,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <deque>
+#include <type_traits>
+#include <vector>
 
 #include "op.h"
 
@@ -55,6 +58,10 @@ static void solve_impl(const hodbf_op &op, int R, const void *b, int64_t ldb, vo
   auto add = [&](size_t b) { need += ((b + 255) & ~size_t(255)) + 256; };
   add(NR * 16);                 // bt
   add(NR * 16);                 // xt
+  add(NR * 16);                 // rt (residual of the last cycle, all columns)
+  add(NR * 16);                 // xc (solution of the cycle's columns)
+  add(size_t(std::max<int64_t>(n, int64_t(m + 1) * m)) * R * 16);  // column-gather staging
+  add(size_t(R) * 4 * 2);                                           // column lists
   add(size_t(m + 1) * NR * 16); // V
   add(size_t(m) * NR * 8);      // Zs
   add(NR * 16);                 // w
@@ -73,6 +80,9 @@ static void solve_impl(const hodbf_op &op, int R, const void *b, int64_t ldb, vo
   char *base = static_cast<char *>(scratch_alloc(need, st));
   Carve cv{base};
   double2 *bt = cv.take<double2>(NR), *xt = cv.take<double2>(NR);
+  double2 *rt = cv.take<double2>(NR), *xc = cv.take<double2>(NR);
+  void *stage = cv.take<double2>(size_t(std::max<int64_t>(n, int64_t(m + 1) * m)) * R);
+  int32_t *colidx = cv.take<int32_t>(R), *keepidx = cv.take<int32_t>(R);
   double2 *V = cv.take<double2>(size_t(m + 1) * NR);
   float2 *Zs = cv.take<float2>(size_t(m) * NR);
   double2 *w = cv.take<double2>(NR);
@@ -104,9 +114,23 @@ static void solve_impl(const hodbf_op &op, int R, const void *b, int64_t ldb, vo
     out.resize(static_cast<size_t>(R));
     for (int q = 0; q < R; ++q) out[size_t(q)] = h[size_t(q)].x;
   };
-  auto applyZ = [&](const float2 *in, double2 *out) {
-    apply_forward_tree(op, in, wf, work, R, st);
-    launch_c64_to_c128(wf, out, NR, st);
+
+  // Host-to-device copies of small host vectors: the source is kept alive until the solve
+  // returns, so its lifetime never depends on when the asynchronous copy reads it.
+  std::deque<std::vector<char>> held;
+  auto upload = [&](void *dst, const void *src, size_t bytes) {
+    if (bytes == 0) return;
+    held.emplace_back(static_cast<const char *>(src), static_cast<const char *>(src) + bytes);
+    HIPCHK(hipMemcpyAsync(dst, held.back().data(), bytes, hipMemcpyHostToDevice, st));
+  };
+  // Gather the columns idx (device, Rd of them) of a [rows][Rs] block into a [rows][Rd]
+  // block at dst (which may overlap src: the gather goes through the staging buffer).
+  auto compact = [&](auto *src, auto *dst, int64_t rows, int Rs, const int32_t *idx, int Rd) {
+    using T = std::remove_pointer_t<decltype(dst)>;
+    T *tmp = static_cast<T *>(stage);
+    launch_gather_cols<T>(src, rows, Rs, idx, Rd, tmp, st);
+    if (rows * Rd > 0)
+      HIPCHK(hipMemcpyAsync(dst, tmp, size_t(rows * Rd) * sizeof(T), hipMemcpyDeviceToDevice, st));
   };
 
   launch_gather(b, true, ldb, bt, true, perm, n, R, st);
@@ -114,71 +138,149 @@ static void solve_impl(const hodbf_op &op, int R, const void *b, int64_t ldb, vo
   std::vector<double> bn2, rn2;
   norms2(bt, bn2);
   std::vector<double> bnorm(static_cast<size_t>(R)), relres(static_cast<size_t>(R), 0.0);
-  std::vector<int32_t> active(static_cast<size_t>(R)), iters(static_cast<size_t>(R), 0), jend(static_cast<size_t>(R));
+  std::vector<int32_t> active(static_cast<size_t>(R)), iters(static_cast<size_t>(R), 0);
   for (int q = 0; q < R; ++q) {
     bnorm[size_t(q)] = std::sqrt(bn2[size_t(q)]);
     if (!std::isfinite(bnorm[size_t(q)])) fail(HODBF_E_NUMERIC, "non-finite right-hand side");
     active[size_t(q)] = bnorm[size_t(q)] > 0 ? 1 : 0;
   }
-  HIPCHK(hipMemcpyAsync(gs.bnorm, bnorm.data(), size_t(R) * 8, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(w, bt, NR * 16, hipMemcpyDeviceToDevice, st));  // r0 = b (x0 = 0)
+  HIPCHK(hipMemcpyAsync(rt, bt, NR * 16, hipMemcpyDeviceToDevice, st));  // r0 = b (x0 = 0)
   int64_t steps = 0;
   bool numeric_bad = false;
+  // Each restart cycle works on the columns still active, stored compactly (Rc columns,
+  // cur[k] = original column of compact column k).  Columns whose estimated residual
+  // meets the tolerance inside a cycle stop iterating; once enough of them have, they
+  // take their least-squares update at once and every per-column array is compacted to
+  // the columns still iterating, so later products run on fewer columns.  Every column
+  // follows the same arithmetic as in a solve of its own.
   while (steps < o.max_iter && std::any_of(active.begin(), active.end(), [](int a) { return a; })) {
-    HIPCHK(hipMemcpyAsync(gs.active, active.data(), size_t(R) * 4, hipMemcpyHostToDevice, st));
-    launch_multidot(w, 0, 1, w, n, R, partial, nblk, st);
-    launch_reduce_partials(partial, nblk, 1, R, sq, 0, st);
+    std::vector<int32_t> act;
+    for (int q = 0; q < R; ++q)
+      if (active[size_t(q)]) act.push_back(q);
+    const int Ra = int(act.size());
+    std::vector<int32_t> cur = act;
+    int Rc = Ra;
+    upload(colidx, act.data(), size_t(Ra) * 4);
+    launch_gather_cols<double2>(rt, n, R, colidx, Ra, w, st);
+    launch_gather_cols<double2>(xt, n, R, colidx, Ra, xc, st);
+    std::vector<double> bsub(static_cast<size_t>(Ra));
+    for (int k = 0; k < Ra; ++k) bsub[size_t(k)] = bnorm[size_t(act[size_t(k)])];
+    std::vector<int32_t> ones(static_cast<size_t>(Ra), 1);
+    upload(gs.bnorm, bsub.data(), size_t(Ra) * 8);
+    upload(gs.active, ones.data(), size_t(Ra) * 4);
+    gs.R = Rc;
+    launch_multidot(w, 0, 1, w, n, Rc, partial, nblk, st);
+    launch_reduce_partials(partial, nblk, 1, Rc, sq, 0, st);
     launch_cycle_init(gs, sq, st);
-    launch_normalize(w, sq, V, nullptr, n, R, nullptr, st);
-    launch_mask_cols(V, gs.active, n, R, st);
+    launch_normalize(w, sq, V, nullptr, n, Rc, nullptr, st);
+    std::vector<int32_t> jend(static_cast<size_t>(Rc));
+    // least-squares update x += Z_k y for the compact columns with jend >= 0 (the others
+    // get y = 0), then their solutions go back to xt and their steps are counted
+    auto finish = [&](int nv, const std::vector<int32_t> &jk) {
+      std::vector<int32_t> jz(jk.size());
+      for (size_t k = 0; k < jk.size(); ++k) jz[k] = jk[k] >= 0 ? jk[k] : 0;
+      upload(gs.jend, jz.data(), jz.size() * 4);
+      launch_lsq(gs, st);
+      launch_xupdate(Zs, n * Rc, nv, gs.y, xc, n, Rc, st);
+      for (size_t k = 0; k < jk.size(); ++k)
+        if (jk[k] >= 0) iters[size_t(cur[k])] += jk[k];
+    };
     int jdone = 0;
     const int jmax = int(std::min<int64_t>(m, o.max_iter - steps));
     for (int j = 0; j < jmax; ++j) {
-      double2 *vj = V + size_t(j) * NR;
-      float2 *zj = Zs + size_t(j) * NR;
-      launch_c128_to_c64(vj, vf, NR, st);
-      if (pre_ft >= 0) apply_precond_tree(op, pre_ft, vf, zj, work, R, st);
-      else HIPCHK(hipMemcpyAsync(zj, vf, NR * 8, hipMemcpyDeviceToDevice, st));
-      applyZ(zj, w);
-      double2 *hcol = gs.H + size_t(j) * (m + 1) * R;
+      const int64_t NRc = n * Rc;
+      double2 *vj = V + size_t(j) * NRc;
+      float2 *zj = Zs + size_t(j) * NRc;
+      launch_c128_to_c64(vj, vf, NRc, st);
+      if (pre_ft >= 0) apply_precond_tree(op, pre_ft, vf, zj, work, Rc, st);
+      else HIPCHK(hipMemcpyAsync(zj, vf, NRc * 8, hipMemcpyDeviceToDevice, st));
+      apply_forward_tree(op, zj, wf, work, Rc, st);
+      launch_c64_to_c128(wf, w, NRc, st);
+      double2 *hcol = gs.H + size_t(j) * (m + 1) * Rc;
       // classical Gram-Schmidt, applied twice
-      launch_multidot(V, NR, j + 1, w, n, R, partial, nblk, st);
-      launch_reduce_partials(partial, nblk, j + 1, R, hcol, 0, st);
-      launch_vupdate(V, NR, j + 1, hcol, w, n, R, st);
-      launch_multidot(V, NR, j + 1, w, n, R, partial, nblk, st);
-      launch_reduce_partials(partial, nblk, j + 1, R, hbuf, 0, st);
-      launch_vupdate(V, NR, j + 1, hbuf, w, n, R, st);
-      launch_reduce_partials(partial, nblk, j + 1, R, hcol, 1, st);
-      launch_multidot(w, 0, 1, w, n, R, partial, nblk, st);
-      launch_reduce_partials(partial, nblk, 1, R, sq, 0, st);
-      launch_normalize(w, sq, V + size_t(j + 1) * NR, hcol + size_t(j + 1) * R, n, R, nullptr, st);
+      launch_multidot(V, NRc, j + 1, w, n, Rc, partial, nblk, st);
+      launch_reduce_partials(partial, nblk, j + 1, Rc, hcol, 0, st);
+      launch_vupdate(V, NRc, j + 1, hcol, w, n, Rc, st);
+      launch_multidot(V, NRc, j + 1, w, n, Rc, partial, nblk, st);
+      launch_reduce_partials(partial, nblk, j + 1, Rc, hbuf, 0, st);
+      launch_vupdate(V, NRc, j + 1, hbuf, w, n, Rc, st);
+      launch_reduce_partials(partial, nblk, j + 1, Rc, hcol, 1, st);
+      launch_multidot(w, 0, 1, w, n, Rc, partial, nblk, st);
+      launch_reduce_partials(partial, nblk, 1, Rc, sq, 0, st);
+      launch_normalize(w, sq, V + size_t(j + 1) * NRc, hcol + size_t(j + 1) * Rc, n, Rc, nullptr,
+                       st);
       launch_givens(gs, j, o.tol, st);
       HIPCHK(hipGetLastError());
-      HIPCHK(hipMemcpyAsync(jend.data(), gs.jend, size_t(R) * 4, hipMemcpyDeviceToHost, st));
+      jend.resize(size_t(Rc));
+      HIPCHK(hipMemcpyAsync(jend.data(), gs.jend, size_t(Rc) * 4, hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
       jdone = j + 1;
-      bool all = true;
-      for (int q = 0; q < R; ++q)
-        if (jend[size_t(q)] < 0) all = false;
-      if (all) break;
+      std::vector<int32_t> keep;
+      for (int k = 0; k < Rc; ++k)
+        if (jend[size_t(k)] < 0) keep.push_back(k);
+      if (keep.empty()) break;
+      const int done = Rc - int(keep.size());
+      if (j + 1 < jmax && done >= std::max(4, Rc / 8)) {
+        // retire the finished columns, then compact to the columns still iterating
+        finish(jdone, jend);
+        std::vector<int32_t> fin;
+        for (int k = 0; k < Rc; ++k)
+          if (jend[size_t(k)] >= 0) fin.push_back(k);
+        std::vector<int32_t> fin_orig;
+        for (int k : fin) fin_orig.push_back(cur[size_t(k)]);
+        upload(keepidx, fin.data(), fin.size() * 4);
+        upload(colidx, fin_orig.data(), fin_orig.size() * 4);
+        double2 *tmp = static_cast<double2 *>(stage);
+        launch_gather_cols<double2>(xc, n, Rc, keepidx, int(fin.size()), tmp, st);
+        launch_scatter_cols<double2>(tmp, n, int(fin.size()), colidx, R, xt, st);
+        const int Rk = int(keep.size());
+        upload(keepidx, keep.data(), size_t(Rk) * 4);
+        for (int i = 0; i <= jdone; ++i)
+          compact(V + size_t(i) * NRc, V + size_t(i) * n * Rk, n, Rc, keepidx, Rk);
+        for (int i = 0; i < jdone; ++i)
+          compact(Zs + size_t(i) * NRc, Zs + size_t(i) * n * Rk, n, Rc, keepidx, Rk);
+        compact(xc, xc, n, Rc, keepidx, Rk);
+        compact(gs.H, gs.H, int64_t(m + 1) * m, Rc, keepidx, Rk);
+        compact(gs.cs, gs.cs, int64_t(m), Rc, keepidx, Rk);
+        compact(gs.sn, gs.sn, int64_t(m), Rc, keepidx, Rk);
+        compact(gs.g, gs.g, int64_t(m + 1), Rc, keepidx, Rk);
+        compact(gs.bnorm, gs.bnorm, 1, Rc, keepidx, Rk);
+        compact(gs.est, gs.est, 1, Rc, keepidx, Rk);
+        compact(gs.active, gs.active, 1, Rc, keepidx, Rk);
+        // the kept columns are still iterating (finish() left 0 in their jend)
+        const std::vector<int32_t> still(static_cast<size_t>(Rk), -1);
+        upload(gs.jend, still.data(), size_t(Rk) * 4);
+        std::vector<int32_t> nc;
+        for (int k : keep) nc.push_back(cur[size_t(k)]);
+        cur = nc;
+        Rc = Rk;
+        gs.R = Rc;
+      }
     }
     // columns still iterating at the cycle cap keep all jdone steps
-    for (int q = 0; q < R; ++q)
-      if (jend[size_t(q)] < 0) jend[size_t(q)] = jdone;
-    HIPCHK(hipMemcpyAsync(gs.jend, jend.data(), size_t(R) * 4, hipMemcpyHostToDevice, st));
-    launch_lsq(gs, st);
-    launch_xupdate(Zs, NR, jdone, gs.y, xt, n, R, st);
-    for (int q = 0; q < R; ++q)
-      if (active[size_t(q)]) iters[size_t(q)] += jend[size_t(q)];
+    for (int k = 0; k < Rc; ++k)
+      if (jend[size_t(k)] < 0) jend[size_t(k)] = jdone;
+    finish(jdone, jend);
+    upload(colidx, cur.data(), size_t(Rc) * 4);
+    launch_scatter_cols<double2>(xc, n, Rc, colidx, R, xt, st);
     steps += jdone;
-    // true residual r = b - Z x
-    launch_c128_to_c64(xt, vf, NR, st);
-    applyZ(vf, w);
-    launch_axpby(bt, w, w, NR, st);
-    norms2(w, rn2);
-    for (int q = 0; q < R; ++q) {
-      if (!active[size_t(q)]) continue;
-      const double rr = std::sqrt(rn2[size_t(q)]) / bnorm[size_t(q)];
+    // true residual r = b - Z x for every column of this cycle
+    upload(colidx, act.data(), size_t(Ra) * 4);
+    launch_gather_cols<double2>(xt, n, R, colidx, Ra, xc, st);
+    launch_c128_to_c64(xc, vf, n * Ra, st);
+    apply_forward_tree(op, vf, wf, work, Ra, st);
+    launch_c64_to_c128(wf, w, n * Ra, st);
+    launch_gather_cols<double2>(bt, n, R, colidx, Ra, xc, st);
+    launch_axpby(xc, w, w, n * Ra, st);
+    launch_scatter_cols<double2>(w, n, Ra, colidx, R, rt, st);
+    launch_multidot(w, 0, 1, w, n, Ra, partial, nblk, st);
+    launch_reduce_partials(partial, nblk, 1, Ra, sq, 0, st);
+    std::vector<double2> h(static_cast<size_t>(Ra));
+    HIPCHK(hipMemcpyAsync(h.data(), sq, size_t(Ra) * 16, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int k = 0; k < Ra; ++k) {
+      const int q = act[size_t(k)];
+      const double rr = std::sqrt(h[size_t(k)].x) / bnorm[size_t(q)];
       relres[size_t(q)] = rr;
       if (!std::isfinite(rr)) {
         numeric_bad = true;

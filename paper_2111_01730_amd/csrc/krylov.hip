@@ -222,6 +222,50 @@ void launch_axpby(const double2 *a, const double2 *b, double2 *out, int64_t coun
   if (count > 0) hipLaunchKernelGGL(k_sub, dim3(grid_for(count)), dim3(256), 0, st, a, b, out, count);
 }
 
+// Column selection on [rows][R]-layout blocks (element (r, q) at r * R + q):
+// gather: dst[r][k] = src[r][idx[k]] (k < Rd); scatter: dst[r][idx[k]] = src[r][k].
+template <typename T>
+__global__ void k_gather_cols(const T *__restrict__ src, int64_t rows, int Rs,
+                              const int32_t *__restrict__ idx, int Rd, T *__restrict__ dst) {
+  const int64_t tot = rows * Rd;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < tot;
+       e += int64_t(gridDim.x) * blockDim.x)
+    dst[e] = src[(e / Rd) * Rs + idx[e % Rd]];
+}
+template <typename T>
+__global__ void k_scatter_cols(const T *__restrict__ src, int64_t rows, int Rs,
+                               const int32_t *__restrict__ idx, int Rd, T *__restrict__ dst) {
+  const int64_t tot = rows * Rs;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < tot;
+       e += int64_t(gridDim.x) * blockDim.x)
+    dst[(e / Rs) * Rd + idx[e % Rs]] = src[e];
+}
+
+template <typename T>
+void launch_gather_cols(const T *src, int64_t rows, int Rs, const int32_t *idx, int Rd, T *dst,
+                        hipStream_t st) {
+  if (rows * Rd > 0)
+    hipLaunchKernelGGL(k_gather_cols<T>, dim3(grid_for(rows * Rd)), dim3(256), 0, st, src, rows,
+                       Rs, idx, Rd, dst);
+}
+template <typename T>
+void launch_scatter_cols(const T *src, int64_t rows, int Rs, const int32_t *idx, int Rd, T *dst,
+                         hipStream_t st) {
+  if (rows * Rs > 0)
+    hipLaunchKernelGGL(k_scatter_cols<T>, dim3(grid_for(rows * Rs)), dim3(256), 0, st, src, rows,
+                       Rs, idx, Rd, dst);
+}
+template void launch_gather_cols<double2>(const double2 *, int64_t, int, const int32_t *, int,
+                                          double2 *, hipStream_t);
+template void launch_gather_cols<float2>(const float2 *, int64_t, int, const int32_t *, int,
+                                         float2 *, hipStream_t);
+template void launch_gather_cols<double>(const double *, int64_t, int, const int32_t *, int,
+                                         double *, hipStream_t);
+template void launch_gather_cols<int32_t>(const int32_t *, int64_t, int, const int32_t *, int,
+                                          int32_t *, hipStream_t);
+template void launch_scatter_cols<double2>(const double2 *, int64_t, int, const int32_t *, int,
+                                           double2 *, hipStream_t);
+
 // ---------------------------------------------------------------------------
 // Per-column GMRES bookkeeping (GmresState), one thread per right-hand side.
 
