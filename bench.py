@@ -37,8 +37,8 @@ PEAK_HBM_GBS = 8000.0
 # HBM bytes of one forward apply of this workload, from the FETCH_SIZE / WRITE_SIZE
 # counter runs recorded in profiles/grouped_mfma_f32_forward_c2_r64_traffic.md (scaled
 # by a 256 MiB copy); valid only while the kernel and packing sources are unchanged.
-MEASURED_TRAFFIC = {"sources_sha256": "b10da65ef67cac988be05300b0e1ed52d923f4da34353d3a36fc1938324a55fa",
-                    "bytes_per_apply": 1608652161.8 + 487268240.0, "launches_per_apply": 10}
+MEASURED_TRAFFIC = {"sources_sha256": "1974f01df8ac4be2e0e75a280b2fc93d3e484ea07b8facc6eba7c9111538dad4",
+                    "bytes_per_apply": 1352961511.6 + 575083392.0, "launches_per_apply": 10}
 
 
 def sources_sha256():

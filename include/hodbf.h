@@ -181,8 +181,10 @@ typedef struct {
   double build_seconds;      /* wall time of the forward construction */
   double precond_seconds;    /* wall time of the preconditioner construction */
   int64_t id_count;          /* interpolative decompositions computed */
-  int64_t io_rows_fwd;       /* sum over stored blocks of (rows + cols) of Z_con: one apply
-                                reads and writes 8 * nrhs * io_rows_fwd vector bytes */
+  int64_t io_rows_fwd;       /* vector rows one apply of Z_con moves: per grouped launch every
+                                output row once and every distinct input row segment once
+                                (blocks that read the same rows share them); one apply reads
+                                and writes 8 * nrhs * io_rows_fwd vector bytes */
   int64_t io_rows_pre;       /* the same for the preconditioner */
 } hodbf_stats_t;
 

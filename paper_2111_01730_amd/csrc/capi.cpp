@@ -374,8 +374,9 @@ hodbf_status hodbf_stats(const hodbf_op *op, hodbf_stats_t *s) {
     s->build_seconds = op->build_seconds;
     s->precond_seconds = op->pre.seconds;
     s->id_count = op->id_count;
-    for (auto &r : op->fwd_table) s->io_rows_fwd += r.m + r.n;
-    for (auto &r : op->pre.table) s->io_rows_pre += r.m + r.n;
+    s->io_rows_fwd = op->fwd.io_rows;
+    s->io_rows_pre = op->pre.leaf.io_rows;
+    for (auto &lv : op->pre.levels) s->io_rows_pre += lv.prog.io_rows;
   });
 }
 

@@ -56,6 +56,9 @@ struct Program {
   std::vector<Launch> launches;
   DevBuf segs, pairs, rowmap;
   int64_t t_rows = 0;  // stage workspace rows
+  // vector rows one apply moves: per launch every output row once and every distinct
+  // input row segment once (stacked blocks share theirs)
+  int64_t io_rows = 0;
   int64_t nseg = 0, npair = 0;
 };
 

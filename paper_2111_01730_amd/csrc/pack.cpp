@@ -10,6 +10,8 @@
 // maps scatter the rows back to each block's own output range.
 #include <algorithm>
 #include <functional>
+#include <set>
+#include <tuple>
 
 #include "pack_sink.h"
 
@@ -232,6 +234,19 @@ void pack_group(PackSink &pk, const Tree &t, const std::vector<const Butterfly *
 }
 
 void upload_program(Program &prog, PackSink &pk, hipStream_t st) {
+  prog.io_rows = 0;
+  for (const Launch &ln : pk.launches) {
+    std::set<std::tuple<int32_t, int32_t, int32_t>> inputs;
+    for (int64_t s = ln.s0; s < ln.s0 + ln.ns; ++s) {
+      const Seg &sg = pk.segs[size_t(s)];
+      prog.io_rows += sg.m;
+      for (int32_t p = sg.p0; p < sg.p1; ++p) {
+        const Pair &pr = pk.pairs[size_t(p)];
+        inputs.insert({pr.in_buf, pr.in_row, pr.n});
+      }
+    }
+    for (auto &in : inputs) prog.io_rows += std::get<2>(in);
+  }
   // sort each launch's segments by row-tile count (their order within a launch is free:
   // they write disjoint rows) and record the class boundaries
   for (Launch &ln : pk.launches) {
