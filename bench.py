@@ -244,6 +244,8 @@ def main():
     if args.mode == "serve":
         return serve_mode(args)
     if args.mode == "config":
+        # multi-minute constructions: the library's progress messages go to stderr
+        os.environ.setdefault("HODBF_LOG", "1")
         return config_mode(args)
     t0 = time.perf_counter()
     op = Operator(g, tol_con=cfg["tol"], tol_fact=args.tol_fact, precond=P_FP32 | P_BF16 | P_FP16,
