@@ -267,22 +267,21 @@ __device__ __forceinline__ unsigned load_chunk(const ChunkSrc &c, int kb, const 
   return msk;
 }
 
-// Work items of one tile class: item it is tile it / nsl with right-hand-side slice
-// it % nsl of RQ (<= 64) columns; this workgroup takes items first, first + stride, ...
-// below end.  The next item's descriptors and first chunk are fetched while the current
-// item's last chunk is multiplied, so a workgroup streams without a gap between tiles.
+// One work item: tile it / nsl with right-hand-side slice it % nsl of RQ (<= 64) columns.
 // The wave owns NRI row tiles (wr, wr + RW, ...) and NCI column tiles (wc, wc + CW), CW =
 // kWaves / RW; all LDS offsets are compile-time immediates from one lane base address.
+// Factor columns and input rows stream through LDS in chunks of kKC; the next chunk
+// (same pair, or the tile's next pair, whose descriptor is read one pair ahead) is
+// fetched into registers while the current one is multiplied.
 template <typename FT, int NRI, int NCI, int RW>
-__device__ __forceinline__ void class_items(int it, const int end, const int stride, const int nsl,
-                                            const int RQ, const Seg *__restrict__ segs,
-                                            const Pair *__restrict__ pairs,
-                                            const RowMap *__restrict__ rowmap,
-                                            const FT *__restrict__ F,
-                                            const float2 *__restrict__ X,
-                                            const float2 *__restrict__ T,
-                                            float2 *__restrict__ OUT, const int R, const int beta,
-                                            const int wr, const int wc, float2 *xs, float2 *as) {
+__device__ __forceinline__ void tile_item(const int it, const int nsl, const int RQ,
+                                          const Seg *__restrict__ segs,
+                                          const Pair *__restrict__ pairs,
+                                          const RowMap *__restrict__ rowmap,
+                                          const FT *__restrict__ F, const float2 *__restrict__ X,
+                                          const float2 *__restrict__ T, float2 *__restrict__ OUT,
+                                          const int R, const int beta, const int wr, const int wc,
+                                          float2 *xs, float2 *as) {
   constexpr int CW = kWaves / RW;
   const int tid = threadIdx.x, lane = tid & 63;
   const int i16 = lane & 15;
@@ -290,157 +289,136 @@ __device__ __forceinline__ void class_items(int it, const int end, const int str
   const int qo = i16 >> 1, op = i16 & 1;
   const float2 *xl = xs + 2 * kk * kXS + wc * 8 + qo;   // this lane's input fragment base
   const float2 *al = as + 2 * kk * kAS + wr * 16 + i16;  // this lane's factor fragment base
-  Seg sg = segs[it / nsl];
-  int q0 = (it % nsl) * RQ;
-  int Rc = min(R - q0, RQ);
+  const Seg sg = segs[it / nsl];
+  const int q0 = (it % nsl) * RQ;
+  const int Rc = min(R - q0, RQ);
   ChunkSrc cur = chunk_src(pairs[sg.p0], R, q0, Rc, sg.m);
   float2 xr[kXL], ar[kAL];
   unsigned msk = load_chunk<FT>(cur, 0, F, X, T, R, xr, ar);
   float lscale = cur.scale;  // factor scale of the chunk held in xr / ar
+  floatx4 acc[NRI > 0 ? NRI * NCI : 1];
+#pragma unroll
+  for (int j = 0; j < (NRI > 0 ? NRI * NCI : 1); ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  int p = sg.p0, k0 = 0;
+  Pair pr1;  // descriptor of the tile's following pair, fetched one pair ahead
+  if (p + 1 < sg.p1) pr1 = pairs[p + 1];
   while (true) {
-    // next item of this workgroup: descriptors now, first chunk with the last chunk below
-    const int itn = it + stride;
-    const bool has_next = itn < end;
-    Seg sgn = sg;
-    int q0n = q0, Rcn = Rc;
-    if (has_next) {
-      sgn = segs[itn / nsl];
-      q0n = (itn % nsl) * RQ;
-      Rcn = min(R - q0n, RQ);
+    __syncthreads();  // previous chunk fully consumed
+#pragma unroll
+    for (int i = 0; i < kXL; ++i) {
+      const int e = tid + kThreads * i;
+      const bool ok = (msk >> i) & 1u;
+      xs[(e >> 6) * kXS + (e & 63)] = make_float2(ok ? xr[i].x : 0.f, ok ? xr[i].y : 0.f);
     }
-    const Pair prn = pairs[sgn.p0];
-    floatx4 acc[NRI > 0 ? NRI * NCI : 1];
 #pragma unroll
-    for (int j = 0; j < (NRI > 0 ? NRI * NCI : 1); ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    int p = sg.p0, k0 = 0;
-    Pair pr1;  // descriptor of the tile's following pair, fetched one pair ahead
-    if (p + 1 < sg.p1) pr1 = pairs[p + 1];
-    while (true) {
-      __syncthreads();  // previous chunk fully consumed
+    for (int i = 0; i < kAL; ++i) {
+      const int e = tid + kThreads * i;
+      const bool ok = (msk >> (kXL + i)) & 1u;
+      as[(e / kTileRows) * kAS + e % kTileRows] =
+          make_float2(ok ? ar[i].x * lscale : 0.f, ok ? ar[i].y * lscale : 0.f);
+    }
+    __syncthreads();
+    // the second half of a chunk past the pair's last column holds only zeros
+    const int nh = k0 + kKC / 2 < cur.n ? 2 : 1;
+    // the next chunk: same pair, or the tile's next pair
+    bool last = false;
+    if (k0 + kKC < cur.n) {
+      k0 += kKC;
+    } else if (p + 1 < sg.p1) {
+      ++p;
+      k0 = 0;
+      cur = chunk_src(pr1, R, q0, Rc, sg.m);
+      if (p + 1 < sg.p1) pr1 = pairs[p + 1];
+    } else {
+      last = true;
+    }
+    if (!last) {
+      msk = load_chunk<FT>(cur, k0, F, X, T, R, xr, ar);
+      lscale = cur.scale;
+    }
+    if (NRI > 0) {
 #pragma unroll
-      for (int i = 0; i < kXL; ++i) {
-        const int e = tid + kThreads * i;
-        const bool ok = (msk >> i) & 1u;
-        xs[(e >> 6) * kXS + (e & 63)] = make_float2(ok ? xr[i].x : 0.f, ok ? xr[i].y : 0.f);
-      }
+      for (int h = 0; h < 2; ++h) {
+        if (h >= nh) break;
+        // this lane's two complex K rows of the half chunk: 8 h + 2 kk and 8 h + 2 kk + 1
+        float2 x0[NCI], x1[NCI];
 #pragma unroll
-      for (int i = 0; i < kAL; ++i) {
-        const int e = tid + kThreads * i;
-        const bool ok = (msk >> (kXL + i)) & 1u;
-        as[(e / kTileRows) * kAS + e % kTileRows] =
-            make_float2(ok ? ar[i].x * lscale : 0.f, ok ? ar[i].y * lscale : 0.f);
-      }
-      __syncthreads();
-      // the second half of a chunk past the pair's last column holds only zeros
-      const int nh = k0 + kKC / 2 < cur.n ? 2 : 1;
-      // the next chunk: same pair, next pair of the tile, or the next item's first
-      bool last = false, fetch = true;
-      if (k0 + kKC < cur.n) {
-        k0 += kKC;
-      } else if (p + 1 < sg.p1) {
-        ++p;
-        k0 = 0;
-        cur = chunk_src(pr1, R, q0, Rc, sg.m);
-        if (p + 1 < sg.p1) pr1 = pairs[p + 1];
-      } else {
-        last = true;
-        fetch = has_next;
-        k0 = 0;
-        cur = chunk_src(prn, R, q0n, Rcn, sgn.m);
-      }
-      if (fetch) {
-        msk = load_chunk<FT>(cur, k0, F, X, T, R, xr, ar);
-        lscale = cur.scale;
-      }
-      if (NRI > 0) {
+        for (int ci = 0; ci < NCI; ++ci) {
+          x0[ci] = xl[8 * h * kXS + ci * CW * 8];
+          x1[ci] = xl[(8 * h + 1) * kXS + ci * CW * 8];
+        }
+        // row tiles in pairs when NCI = 1: every step interleaves at least two
+        // accumulators, so no MFMA waits on the one just issued
+        constexpr int JG = NCI == 1 && NRI > 1 ? 2 : 1;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          if (h >= nh) break;
-          // this lane's two complex K rows of the half chunk: 8 h + 2 kk and 8 h + 2 kk + 1
-          float2 x0[NCI], x1[NCI];
+        for (int j0 = 0; j0 < NRI; j0 += JG) {
+          float2 a0[JG], a1[JG];
 #pragma unroll
-          for (int ci = 0; ci < NCI; ++ci) {
-            x0[ci] = xl[8 * h * kXS + ci * CW * 8];
-            x1[ci] = xl[(8 * h + 1) * kXS + ci * CW * 8];
+          for (int u = 0; u < JG; ++u) {
+            const int j = j0 + u < NRI ? j0 + u : j0;
+            a0[u] = al[8 * h * kAS + j * RW * 16];
+            a1[u] = al[(8 * h + 1) * kAS + j * RW * 16];
           }
-          // row tiles in pairs when NCI = 1: every step interleaves at least two
-          // accumulators, so no MFMA waits on the one just issued
-          constexpr int JG = NCI == 1 && NRI > 1 ? 2 : 1;
 #pragma unroll
-          for (int j0 = 0; j0 < NRI; j0 += JG) {
-            float2 a0[JG], a1[JG];
+          for (int t = 0; t < 4; ++t) {
 #pragma unroll
             for (int u = 0; u < JG; ++u) {
-              const int j = j0 + u < NRI ? j0 + u : j0;
-              a0[u] = al[8 * h * kAS + j * RW * 16];
-              a1[u] = al[(8 * h + 1) * kAS + j * RW * 16];
-            }
+              if (j0 + u < NRI) {
+                const float2 a = t < 2 ? a0[u] : a1[u];
+                const float av = (t & 1) ? a.y : a.x;
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-#pragma unroll
-              for (int u = 0; u < JG; ++u) {
-                if (j0 + u < NRI) {
-                  const float2 a = t < 2 ? a0[u] : a1[u];
-                  const float av = (t & 1) ? a.y : a.x;
-#pragma unroll
-                  for (int ci = 0; ci < NCI; ++ci) {
-                    const float2 x = t < 2 ? x0[ci] : x1[ci];
-                    const float bv = (t & 1) ? (op ? x.x : -x.y) : (op ? x.y : x.x);
-                    const int j = (j0 + u) * NCI + ci;
-                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[j], 0, 0, 0);
-                  }
+                for (int ci = 0; ci < NCI; ++ci) {
+                  const float2 x = t < 2 ? x0[ci] : x1[ci];
+                  const float bv = (t & 1) ? (op ? x.x : -x.y) : (op ? x.y : x.x);
+                  const int j = (j0 + u) * NCI + ci;
+                  acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[j], 0, 0, 0);
                 }
               }
             }
           }
         }
       }
-      if (last) break;
     }
-    {
-      // the tile's row map (at most kMaxMapEntries entries, read with uniform loads;
-      // the array is padded past its end) resolved per row in registers; accumulation
-      // into the output is a non-returning atomic add (each output element belongs to
-      // exactly one item, so it is a plain read-modify-write with nothing to wait on)
-      const int ne = sg.map1 - sg.map0;
-      int mstart[kMaxMapEntries], mbase[kMaxMapEntries];
+    if (last) break;
+  }
+  {
+    // the tile's row map (at most kMaxMapEntries entries, read with uniform loads;
+    // the array is padded past its end) resolved per row in registers; accumulation
+    // into the output is a non-returning atomic add (each output element belongs to
+    // exactly one item, so it is a plain read-modify-write with nothing to wait on)
+    const int ne = sg.map1 - sg.map0;
+    int mstart[kMaxMapEntries], mbase[kMaxMapEntries];
 #pragma unroll
-      for (int k = 0; k < kMaxMapEntries; ++k) {
-        const RowMap e = rowmap[sg.map0 + k];
-        mstart[k] = k < ne ? e.start : kTileRows;
-        mbase[k] = e.out_row - e.start;
-      }
+    for (int k = 0; k < kMaxMapEntries; ++k) {
+      const RowMap e = rowmap[sg.map0 + k];
+      mstart[k] = k < ne ? e.start : kTileRows;
+      mbase[k] = e.out_row - e.start;
+    }
 #pragma unroll
-      for (int ri = 0; ri < NRI; ++ri) {
-        const int rt = wr + ri * RW;
+    for (int ri = 0; ri < NRI; ++ri) {
+      const int rt = wr + ri * RW;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int row = rt * 16 + 4 * kk + v;
-          int base = mbase[0];
+      for (int v = 0; v < 4; ++v) {
+        const int row = rt * 16 + 4 * kk + v;
+        int base = mbase[0];
 #pragma unroll
-          for (int k = 1; k < kMaxMapEntries; ++k) base = mstart[k] <= row ? mbase[k] : base;
-          if (row < sg.m) {
-            const int64_t orow = int64_t(base) + row;
+        for (int k = 1; k < kMaxMapEntries; ++k) base = mstart[k] <= row ? mbase[k] : base;
+        if (row < sg.m) {
+          const int64_t orow = int64_t(base) + row;
 #pragma unroll
-            for (int ci = 0; ci < NCI; ++ci) {
-              const int q = q0 + (wc + ci * CW) * 8 + qo;
-              if (q < q0 + Rc) {
-                float *o = reinterpret_cast<float *>(OUT + orow * R + q) + op;
-                if (beta)
-                  unsafeAtomicAdd(o, acc[ri * NCI + ci][v]);
-                else
-                  *o = acc[ri * NCI + ci][v];
-              }
+          for (int ci = 0; ci < NCI; ++ci) {
+            const int q = q0 + (wc + ci * CW) * 8 + qo;
+            if (q < q0 + Rc) {
+              float *o = reinterpret_cast<float *>(OUT + orow * R + q) + op;
+              if (beta)
+                unsafeAtomicAdd(o, acc[ri * NCI + ci][v]);
+              else
+                *o = acc[ri * NCI + ci][v];
             }
           }
         }
       }
     }
-    if (!has_next) break;
-    it = itn;
-    sg = sgn;
-    q0 = q0n;
-    Rc = Rcn;
   }
 }
 
@@ -455,15 +433,14 @@ __device__ __forceinline__ int xcd_work_index() {
   return ((l / kXcdGroup) * kNumXcd + x) * kXcdGroup + l % kXcdGroup;
 }
 
-// Persistent grouped launch.  The tiles of a launch are sorted by their row-tile count
-// nrt (classes 1..kWaves); class c owns the workgroups [wg0[c], wg0[c + 1]) and the tiles
-// [seg0[c], seg0[c + 1]).  Within a class every wave has a fixed share of the tile's
-// 16 x 8 output tiles, so one loop instantiation serves all of its items; a narrower last
-// slice runs the full-slice instantiation (the extra column tiles read zeros and are not
-// stored).
+// Grouped launch: one workgroup per work item.  The tiles of a launch are sorted by their
+// row-tile count nrt (classes 1..kWaves); class c holds the tiles [seg0[c], seg0[c + 1]),
+// i.e. the work items [seg0[c] nsl, seg0[c + 1] nsl).  Within a class every wave has a
+// fixed share of the tile's 16 x 8 output tiles, so one instantiation serves all of its
+// items; a narrower last slice runs the full-slice instantiation (the extra column tiles
+// read zeros and are not stored).
 struct TileClasses {
   int seg0[kWaves + 1];
-  int wg0[kWaves + 1];
 };
 
 template <typename FT>
@@ -474,14 +451,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
   __shared__ float2 xs[kKC * kXS];
   __shared__ float2 as[kKC * kAS];
   // neighbouring work on one XCD (see xcd_work_index); the padded grid's extra blocks exit
-  const int g = xcd_work_index();
-  if (g >= tc.wg0[kWaves]) return;
+  const int it = xcd_work_index();
+  if (it >= tc.seg0[kWaves] * nsl) return;
   int c = 0;
-  while (c < kWaves - 1 && g >= tc.wg0[c + 1]) ++c;
-  const int first = tc.seg0[c] * nsl + (g - tc.wg0[c]);
-  const int end = tc.seg0[c + 1] * nsl;
-  const int stride = tc.wg0[c + 1] - tc.wg0[c];
-  if (first >= end) return;
+  while (c < kWaves - 1 && it >= tc.seg0[c + 1] * nsl) ++c;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nrt = c + 1;
   const int nnt = ((R < RQ ? R : RQ) + 7) >> 3;  // column tiles of a full slice
@@ -496,8 +469,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
   const int nci = wc < nnt ? (wc + cw < nnt ? 2 : 1) : 0;
   const int sel = nci == 0 ? 0 : nri * 2 + (nci - 1);  // wave-uniform
 #define HODBF_CLASS(NR, NC, RWV)                                                             \
-  class_items<FT, NR, NC, RWV>(first, end, stride, nsl, RQ, segs, pairs, rowmap, F, X, T, OUT, \
-                               R, beta, wr, wc, xs, as)
+  tile_item<FT, NR, NC, RWV>(it, nsl, RQ, segs, pairs, rowmap, F, X, T, OUT, R, beta, wr, wc, xs, \
+                             as)
   if (rw == 1) {
     switch (sel) {
       case 2: HODBF_CLASS(1, 1, 1); break;
@@ -657,33 +630,11 @@ void launch_grouped(const Seg *segs, const Pair *pairs, const RowMap *rowmap, in
   while (RQ > 16 && ns * ((R + RQ - 1) / RQ) < min_wg) RQ >>= 1;
   if (RQ > R) RQ = R;
   const int nsl = (R + RQ - 1) / RQ;
-  // cap on workgroups per launch (each then loops over several items); by default one
-  // workgroup per item, which measured faster than a resident-sized grid (the hardware
-  // dispatcher balances the uneven items)
-  static const int64_t resident = [] {
-    const char *e = std::getenv("HODBF_PERSIST_WORKGROUPS");  // tuning knob, 0 = no cap
-    return e ? int64_t(std::atoll(e)) : int64_t(0);
-  }();
-  // workgroups per class: one per item when the launch fits the resident set, else in
-  // proportion to the class's items (at least one per non-empty class)
-  int64_t items[kRowClasses];
-  for (int c = 0; c < kRowClasses; ++c) items[c] = (cls[c + 1] - cls[c]) * nsl;
-  const int64_t total = ns * nsl;
-  const bool fits = resident <= 0 || total <= resident;
   TileClasses tc{};
-  int64_t acc = 0;
-  for (int c = 0; c < kRowClasses; ++c) {
-    tc.seg0[c] = int(cls[c]);
-    tc.wg0[c] = int(acc);
-    const int64_t g = fits || items[c] == 0
-                          ? items[c]
-                          : std::min(items[c], std::max<int64_t>(1, resident * items[c] / total));
-    acc += g;
-  }
-  tc.seg0[kRowClasses] = int(cls[kRowClasses]);
-  tc.wg0[kRowClasses] = int(acc);
+  for (int c = 0; c <= kRowClasses; ++c) tc.seg0[c] = int(cls[c]);
+  const int64_t items = ns * nsl;  // one workgroup per work item
   constexpr int64_t gq = kNumXcd * kXcdGroup;
-  const dim3 grid{unsigned((acc + gq - 1) / gq * gq)};
+  const dim3 grid{unsigned((items + gq - 1) / gq * gq)};
   if (ftype == FT_C64)
     hipLaunchKernelGGL(k_grouped_mfma_f32<float2>, grid, dim3(kThreads), 0, st, sp, pairs, rowmap,
                        static_cast<const float2 *>(F), X, T, OUT, R, beta, RQ, nsl, tc);
