@@ -18,8 +18,21 @@ def _check(name, fft_cols):
     g = cfg["grid"]
     print(f"[{name}: build N={g.n}]", flush=True)
     op = Operator(g, tol_con=cfg["tol"], seed=cfg["seed"])
+    st = op.stats()
+    print(f"[{name}: built in {st['build_seconds']:.1f} s, {st['entries_fwd']} entries, "
+          f"max rank {st['max_rank']}]", flush=True)
     b = op.plane_wave(cfg["dirs"])  # the workload's plane waves, all columns at once
-    y = op.apply(b).cpu().numpy()
+    y = op.apply(b)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        op.apply(b)
+    e1.record()
+    torch.cuda.synchronize()
+    print(f"[{name}: apply with R={b.shape[1]}: {e0.elapsed_time(e1) / 5:.2f} ms incl. "
+          f"permutations]", flush=True)
+    y = y.cpu().numpy()
     bn = b.cpu().numpy()
     rows = cfg["rows"]
     print(f"[{name}: direct sums on {len(rows)} rows]", flush=True)
@@ -30,7 +43,7 @@ def _check(name, fft_cols):
         yf = vie.fft_matvec(g, bn[:, q])
         e = np.linalg.norm(y[:, q] - yf) / np.linalg.norm(yf)
         assert e <= 10 * cfg["tol"], (q, e)
-    return op.stats()
+    return st
 
 
 def test_c3_sphere_64_forward_apply_full_size():
