@@ -159,11 +159,13 @@ static void pack_forward(hodbf_op &op, FwdPlan &fp, hipStream_t st) {
       host[size_t(off) + e] = make_float2(float(f.v[e].real()), float(f.v[e].imag()));
     return off;
   };
-  // device-generated blocks get provisional offsets in region 2; rebased below
+  // device-generated blocks get provisional offsets kDevRegion + off in region 2, rebased
+  // below (a positive bias, so row offsets added while packing carry over)
+  constexpr int64_t kDevRegion = int64_t(1) << 60;
   pk.reserve_dev = [&](int64_t m, int64_t n) -> int64_t {
     const int64_t off = align16(dev_size);
     dev_size = off + m * n;
-    return -1 - off;
+    return kDevRegion + off;
   };
   pk.jobs = &jobs;
   pk.jobcols = &jobcols;
@@ -176,7 +178,7 @@ static void pack_forward(hodbf_op &op, FwdPlan &fp, hipStream_t st) {
     md[3] = 0;
   });
   const int64_t base2 = align16(int64_t(host.size()));
-  auto rebase = [&](int64_t off) { return off < 0 ? base2 + (-1 - off) : off; };
+  auto rebase = [&](int64_t off) { return off >= kDevRegion ? base2 + (off - kDevRegion) : off; };
   for (auto &p : pk.pairs) p.f_off = rebase(p.f_off);
   for (auto &j : jobs) j.f_off = rebase(j.f_off);
   for (auto &r : op.fwd_table) r.off = rebase(r.off);

@@ -94,6 +94,54 @@ void emit_group(PackSink &pk, const std::vector<Member> &mem, int32_t in_buf, in
 
 }  // namespace
 
+// Re-emit every launch's tiles; in a launch with fewer than `below` tiles, a tile taller
+// than `rows` is cut into tiles of at most `rows` rows (each keeps all of its pairs,
+// offset to its rows, and the matching part of its row map).  Row tiles re-read only
+// the (small) input rows, where right-hand-side slices would re-read the factors.
+void retile(PackSink &pk, int64_t below, int rows) {
+  std::vector<Seg> segs;
+  std::vector<Pair> pairs;
+  std::vector<RowMap> maps;
+  segs.reserve(pk.segs.size());
+  pairs.reserve(pk.pairs.size());
+  maps.reserve(pk.rowmap.size());
+  for (Launch &ln : pk.launches) {
+    const int32_t lim = ln.ns < below ? rows : kTileRows;
+    const int64_t s0 = int64_t(segs.size());
+    for (int64_t si = ln.s0; si < ln.s0 + ln.ns; ++si) {
+      const Seg &s = pk.segs[size_t(si)];
+      for (int32_t r0 = 0; r0 < s.m || (s.m == 0 && r0 == 0); r0 += lim) {
+        const int32_t r1 = std::min(s.m, r0 + lim);
+        Seg t{};
+        t.m = r1 - r0;
+        t.p0 = int32_t(pairs.size());
+        for (int32_t p = s.p0; p < s.p1; ++p) {
+          Pair q = pk.pairs[size_t(p)];
+          q.f_off += r0;  // column-major blocks: the tile's rows start r0 further
+          pairs.push_back(q);
+        }
+        t.p1 = int32_t(pairs.size());
+        t.map0 = int32_t(maps.size());
+        for (int32_t e = s.map0; e < s.map1; ++e) {
+          const RowMap &me = pk.rowmap[size_t(e)];
+          const int32_t end = e + 1 < s.map1 ? pk.rowmap[size_t(e + 1)].start : s.m;
+          if (end <= r0 || me.start >= std::max(r1, r0 + 1)) continue;
+          const int32_t st = std::max(me.start, r0);
+          maps.push_back({st - r0, me.out_row + (st - me.start)});
+        }
+        t.map1 = int32_t(maps.size());
+        segs.push_back(t);
+        if (s.m == 0) break;
+      }
+    }
+    ln.s0 = s0;
+    ln.ns = int64_t(segs.size()) - s0;
+  }
+  pk.segs.swap(segs);
+  pk.pairs.swap(pairs);
+  pk.rowmap.swap(maps);
+}
+
 // Pack one set of butterflies whose row and column trees end at the leaves of T_H.
 // meta(bf) gives (l, i, ca, cb) for the block table.
 void pack_group(PackSink &pk, const Tree &t, const std::vector<const Butterfly *> &bfs,
@@ -234,6 +282,7 @@ void pack_group(PackSink &pk, const Tree &t, const std::vector<const Butterfly *
 }
 
 void upload_program(Program &prog, PackSink &pk, hipStream_t st) {
+  retile(pk, kRetileBelow, kTileRows / 2);
   prog.io_rows = 0;
   for (const Launch &ln : pk.launches) {
     std::set<std::tuple<int32_t, int32_t, int32_t>> inputs;

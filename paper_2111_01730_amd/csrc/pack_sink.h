@@ -27,5 +27,10 @@ void pack_group(PackSink &pk, const Tree &t, const std::vector<const Butterfly *
                 bool forward, int final_beta,
                 const std::function<void(const Butterfly &, int64_t *)> &meta);
 void upload_program(Program &prog, PackSink &pk, hipStream_t st);
+// Launches with fewer tiles than this get half-height tiles at upload (more workgroups).
+constexpr int64_t kRetileBelow = 1024;
+// Re-emit every launch's tiles, cutting those of launches with fewer than `below` tiles
+// into tiles of at most `rows` rows (pairs offset to the rows, row maps clipped).
+void retile(PackSink &pk, int64_t below, int rows);
 
 }  // namespace hodbf
