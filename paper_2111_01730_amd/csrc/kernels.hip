@@ -602,17 +602,14 @@ void launch_grouped(const Seg *segs, const Pair *pairs, const RowMap *rowmap, in
                     const float2 *T, float2 *OUT, int R, int beta, hipStream_t st) {
   if (ns <= 0 || R <= 0) return;
   const Seg *sp = segs + s0;
-  if (R < 4) {
+  // FP32 and FP16-stored factors take the MFMA kernel at every R (at R < 8 its extra
+  // column tiles read clamped inputs and are not stored: MFMA work is wasted, but a
+  // product with few columns is bound by streaming the factors, which that kernel does
+  // best); BF16 factors below 4 columns use the vector kernel.
+  if (R < 4 && ftype == FT_BF16) {
     const int64_t nb = (ns + 3) / 4;
-    if (ftype == FT_C64)
-      hipLaunchKernelGGL(k_grouped_gemv<float2>, dim3(unsigned(nb)), dim3(256), 0, st, sp, pairs,
-                         rowmap, static_cast<const float2 *>(F), X, T, OUT, R, beta, ns);
-    else if (ftype == FT_BF16)
-      hipLaunchKernelGGL(k_grouped_gemv<FBF16>, dim3(unsigned(nb)), dim3(256), 0, st, sp, pairs,
-                         rowmap, static_cast<const FBF16 *>(F), X, T, OUT, R, beta, ns);
-    else
-      hipLaunchKernelGGL(k_grouped_gemv<FF16>, dim3(unsigned(nb)), dim3(256), 0, st, sp, pairs,
-                         rowmap, static_cast<const FF16 *>(F), X, T, OUT, R, beta, ns);
+    hipLaunchKernelGGL(k_grouped_gemv<FBF16>, dim3(unsigned(nb)), dim3(256), 0, st, sp, pairs,
+                       rowmap, static_cast<const FBF16 *>(F), X, T, OUT, R, beta, ns);
     return;
   }
   if (ftype == FT_BF16) {
