@@ -7,21 +7,6 @@
 
 namespace hodbf {
 
-// One output tile of a grouped complex GEMM: m <= 128 rows, the sum over pairs
-// [p0, p1) of A_p * in_p.  Its rows are scattered by the row map entries
-// [map0, map1) (sorted by start): local row r goes to out_row + r - start of the last
-// entry with start <= r, so one tile can hold several stacked blocks that read the
-// same input rows.
-struct Seg {
-  int32_t m, p0, p1, map0, map1, pad0, pad1, pad2;
-};
-struct RowMap {
-  int32_t start, out_row;
-};
-constexpr int kTileRows = 64;  // rows of one workgroup tile; leaves hold at most 64 rows
-constexpr int kRowClasses = kTileRows / 16;  // tiles of 1..kRowClasses 16-row MFMA tiles
-constexpr int kMaxMapEntries = 8;  // row map entries of one tile (the array is padded by as many)
-
 // A factor block (column-major, element (i, k) at f_off + k * lda + i, stored values
 // multiplied by scale on load) times the input rows [in_row, in_row + n) of buffer X
 // (in_buf = 0) or T (in_buf = 1).
@@ -31,6 +16,23 @@ struct Pair {
   float scale;
   int32_t pad;
 };
+
+// One output tile of a grouped complex GEMM: m <= 128 rows, the sum over pairs
+// [p0, p1) of A_p * in_p.  Its rows are scattered by the row map entries
+// [map0, map1) (sorted by start): local row r goes to out_row + r - start of the last
+// entry with start <= r, so one tile can hold several stacked blocks that read the
+// same input rows.
+struct Seg {
+  int32_t m, p0, p1, map0, map1, pad0, pad1, pad2;
+  Pair first;  // copy of pairs[p0] (set at upload): one dependent load less per tile
+};
+struct RowMap {
+  int32_t start, out_row;
+};
+constexpr int kTileRows = 64;  // rows of one workgroup tile; leaves hold at most 64 rows
+constexpr int kRowClasses = kTileRows / 16;  // tiles of 1..kRowClasses 16-row MFMA tiles
+constexpr int kMaxMapEntries = 8;  // row map entries of one tile (the array is padded by as many)
+
 
 // Device entry-generation job: column-major block of Z, rows r0..r0+m (tree order,
 // contiguous), columns cols[c_off .. c_off + n) (tree positions).

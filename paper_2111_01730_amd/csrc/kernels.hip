@@ -292,7 +292,7 @@ __device__ __forceinline__ void tile_item(const int it, const int nsl, const int
   const Seg sg = segs[it / nsl];
   const int q0 = (it % nsl) * RQ;
   const int Rc = min(R - q0, RQ);
-  ChunkSrc cur = chunk_src(pairs[sg.p0], R, q0, Rc, sg.m);
+  ChunkSrc cur = chunk_src(sg.first, R, q0, Rc, sg.m);
   float2 xr[kXL], ar[kAL];
   unsigned msk = load_chunk<FT>(cur, 0, F, X, T, R, xr, ar);
   float lscale = cur.scale;  // factor scale of the chunk held in xr / ar

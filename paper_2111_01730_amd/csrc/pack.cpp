@@ -283,6 +283,8 @@ void pack_group(PackSink &pk, const Tree &t, const std::vector<const Butterfly *
 
 void upload_program(Program &prog, PackSink &pk, hipStream_t st) {
   retile(pk, kRetileBelow, kTileRows / 2);
+  for (Seg &sg : pk.segs)
+    if (sg.p1 > sg.p0) sg.first = pk.pairs[size_t(sg.p0)];
   prog.io_rows = 0;
   for (const Launch &ln : pk.launches) {
     std::set<std::tuple<int32_t, int32_t, int32_t>> inputs;
