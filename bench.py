@@ -37,8 +37,8 @@ PEAK_HBM_GBS = 8000.0
 # HBM bytes of one forward apply of this workload, from the FETCH_SIZE / WRITE_SIZE
 # counter runs recorded in profiles/grouped_mfma_f32_forward_c2_r64_traffic.md (scaled
 # by a 256 MiB copy); valid only while the kernel and packing sources are unchanged.
-MEASURED_TRAFFIC = {"sources_sha256": "1974f01df8ac4be2e0e75a280b2fc93d3e484ea07b8facc6eba7c9111538dad4",
-                    "bytes_per_apply": 1352961511.6 + 575083392.0, "launches_per_apply": 10}
+MEASURED_TRAFFIC = {"sources_sha256": "9dbc60c1eb36000551b7affe7da71bb7eb34b1a4515dce2b19d53d05b729f193",
+                    "bytes_per_apply": 1317319013.3 + 435986064.0, "launches_per_apply": 10}
 
 
 def sources_sha256():
