@@ -209,6 +209,23 @@ void hodbf_free(hodbf_op *op);
 const char *hodbf_last_error(void);
 
 /*
+ * hodbf_set_allocator -- route the library's device memory through the caller's
+ * allocator (e.g. a framework's caching allocator, so one pool owns the bytes).
+ * alloc(bytes, stream, ctx) returns device memory (NULL on failure, reported as
+ * E_NOMEM); stream is the stream the memory is first used on, or NULL for operator
+ * arenas used on any stream.  release(ptr, ctx) returns it; stream-ordered reuse is the
+ * allocator's business (scratch is released after the call's last use was enqueued on
+ * its stream).  Operator arenas remember the hook they were allocated with; per-call
+ * workspace uses the hook installed when the call runs, so change it only while no
+ * call is running.  alloc == NULL restores hipMalloc / hipMallocAsync.  The dense
+ * factorisations of the preconditioner construction keep their own rocSOLVER
+ * temporaries.  E_ARG if alloc is set and release is not.  Process-wide, thread-safe.
+ */
+typedef void *(*hodbf_alloc_fn)(size_t bytes, void *stream, void *ctx);
+typedef void (*hodbf_free_fn)(void *ptr, void *ctx);
+hodbf_status hodbf_set_allocator(hodbf_alloc_fn alloc, hodbf_free_fn release, void *ctx);
+
+/*
  * hodbf_plan_probe -- run only the host part of the forward construction (cluster
  * tree, row sampling, interpolative decompositions) and export it, without touching
  * a GPU.  which: 0 perm (int32 N); 1 block table (as above, kind 3 rows give the

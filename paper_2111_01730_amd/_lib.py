@@ -17,7 +17,12 @@ P_NONE, P_FP32, P_BF16, P_BOTH, P_FP16 = 0, 1, 2, 3, 4
 
 EXPORTED = ["hodbf_build", "hodbf_apply", "hodbf_precond_apply", "vie_solve", "hodbf_plane_wave",
             "hodbf_apply_tree",
-            "hodbf_stats", "hodbf_export", "hodbf_free", "hodbf_last_error", "hodbf_plan_probe"]
+            "hodbf_stats", "hodbf_export", "hodbf_free", "hodbf_last_error", "hodbf_plan_probe",
+            "hodbf_set_allocator"]
+
+# allocator hook types: alloc(bytes, stream, ctx) -> device pointer; release(ptr, ctx)
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 
 class BuildParams(C.Structure):
@@ -78,11 +83,13 @@ def lib():
     L.hodbf_export.argtypes = [vp, i32, vp, C.POINTER(C.c_size_t)]
     L.hodbf_plan_probe.argtypes = [C.POINTER(BuildParams), i32, vp, C.POINTER(C.c_size_t)]
     L.hodbf_apply_tree.argtypes = [vp, i32, i32, vp, vp, vp]
+    L.hodbf_set_allocator.argtypes = [ALLOC_FN, FREE_FN, vp]
     L.hodbf_free.argtypes = [vp]
     L.hodbf_free.restype = None
     L.hodbf_last_error.restype = C.c_char_p
     for name in ["hodbf_build", "hodbf_apply", "hodbf_precond_apply", "vie_solve", "hodbf_apply_tree",
-                 "hodbf_plane_wave", "hodbf_stats", "hodbf_export", "hodbf_plan_probe"]:
+                 "hodbf_plane_wave", "hodbf_stats", "hodbf_export", "hodbf_plan_probe",
+                 "hodbf_set_allocator"]:
         getattr(L, name).restype = C.c_int
     _lib = L
     return L

@@ -63,16 +63,43 @@ static hodbf_status guarded(F &&f) {
 }
 
 // ---------------------------------------------------------------------------
-// device buffers
+// device memory: the caller's allocator hook when one is installed, else the HIP runtime
+namespace {
+struct AllocHook {
+  hodbf_alloc_fn alloc = nullptr;
+  hodbf_free_fn release = nullptr;
+  void *ctx = nullptr;
+};
+std::mutex g_hook_mu;
+AllocHook g_hook;
+AllocHook current_hook() {
+  std::lock_guard<std::mutex> lk(g_hook_mu);
+  return g_hook;
+}
+}  // namespace
+
 void DevBuf::reset() {
-  if (p) (void)hipFree(p);
+  if (p) {
+    if (release) release(p, ctx);
+    else (void)hipFree(p);
+  }
   p = nullptr;
   bytes = 0;
+  release = nullptr;
+  ctx = nullptr;
 }
 void DevBuf::alloc(size_t nbytes) {
   reset();
   if (nbytes == 0) return;
-  HIPCHK(hipMalloc(&p, nbytes));
+  const AllocHook h = current_hook();
+  if (h.alloc) {
+    p = h.alloc(nbytes, nullptr, h.ctx);
+    if (!p) fail(HODBF_E_NOMEM, "allocator hook returned NULL");
+    release = h.release;
+    ctx = h.ctx;
+  } else {
+    HIPCHK(hipMalloc(&p, nbytes));
+  }
   bytes = nbytes;
 }
 void DevBuf::upload(const void *src, size_t nbytes, hipStream_t st) {
@@ -86,11 +113,20 @@ void DevBuf::upload(const void *src, size_t nbytes, hipStream_t st) {
 void *scratch_alloc(size_t bytes, hipStream_t st) {
   void *p = nullptr;
   if (bytes == 0) bytes = 256;
-  HIPCHK(hipMallocAsync(&p, bytes, st));
+  const AllocHook h = current_hook();
+  if (h.alloc) {
+    p = h.alloc(bytes, st, h.ctx);
+    if (!p) fail(HODBF_E_NOMEM, "allocator hook returned NULL");
+  } else {
+    HIPCHK(hipMallocAsync(&p, bytes, st));
+  }
   return p;
 }
 void scratch_free(void *p, hipStream_t st) {
-  if (p) (void)hipFreeAsync(p, st);
+  if (!p) return;
+  const AllocHook h = current_hook();
+  if (h.alloc) h.release(p, h.ctx);
+  else (void)hipFreeAsync(p, st);
 }
 
 
@@ -241,6 +277,16 @@ hodbf_status hodbf_build(const hodbf_build_params *params, hodbf_op **out) {
 }
 
 void hodbf_free(hodbf_op *op) { delete op; }
+
+hodbf_status hodbf_set_allocator(hodbf_alloc_fn alloc, hodbf_free_fn release, void *ctx) {
+  return guarded([&] {
+    if (alloc && !release) fail(HODBF_E_ARG, "allocator hook without a release function");
+    std::lock_guard<std::mutex> lk(g_hook_mu);
+    g_hook.alloc = alloc;
+    g_hook.release = alloc ? release : nullptr;
+    g_hook.ctx = alloc ? ctx : nullptr;
+  });
+}
 
 const char *hodbf_last_error(void) { return g_last_error.c_str(); }
 

@@ -15,23 +15,31 @@ void hip_check(hipError_t e, const char *what);
 #define HIPCHK(x) ::hodbf::hip_check((x), #x)
 
 // Owning device allocation.
+// A device allocation: through the allocator hook installed when it was made (release
+// and ctx remembered), else hipMalloc / hipFree.
 struct DevBuf {
   void *p = nullptr;
   size_t bytes = 0;
+  hodbf_free_fn release = nullptr;
+  void *ctx = nullptr;
   DevBuf() = default;
   DevBuf(const DevBuf &) = delete;
   DevBuf &operator=(const DevBuf &) = delete;
-  DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes) {
+  DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes), release(o.release), ctx(o.ctx) {
     o.p = nullptr;
     o.bytes = 0;
+    o.release = nullptr;
   }
   DevBuf &operator=(DevBuf &&o) noexcept {
     if (this != &o) {
       reset();
       p = o.p;
       bytes = o.bytes;
+      release = o.release;
+      ctx = o.ctx;
       o.p = nullptr;
       o.bytes = 0;
+      o.release = nullptr;
     }
     return *this;
   }

@@ -15,6 +15,32 @@ from . import _lib
 from ._lib import C64, C128, P_BF16, P_BOTH, P_FP16, P_FP32, P_NONE, check, lib
 
 
+_hook_refs: list = []  # the installed ctypes callbacks must outlive their use
+
+
+def use_torch_allocator(enable: bool = True) -> None:
+    """Route the library's device memory (operator arenas and per-call workspace) through
+    torch's caching allocator, so torch's pool owns and accounts for the bytes; False
+    restores hipMalloc.  Change it only while no library call is running."""
+    if not enable:
+        check(lib().hodbf_set_allocator(_lib.ALLOC_FN(0), _lib.FREE_FN(0), None))
+        _hook_refs.clear()
+        return
+
+    def _alloc(nbytes, stream, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+        except Exception:  # reported to the caller of the library as E_NOMEM
+            return None
+
+    def _free(ptr, ctx):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    a, f = _lib.ALLOC_FN(_alloc), _lib.FREE_FN(_free)
+    check(lib().hodbf_set_allocator(a, f, None))
+    _hook_refs[:] = [a, f]
+
+
 def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 

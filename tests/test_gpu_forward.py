@@ -159,3 +159,35 @@ def test_gmres_zero_rhs_column(hod):
     x, info = op.solve(b, tol=1e-5, use_precond=0)  # above the FP32 apply floor (~1e-7)
     assert info["converged"].all()
     assert torch.count_nonzero(x[:, 1]).item() == 0
+
+
+def test_allocator_hook_routes_memory_through_torch(ragged, hod):
+    """hodbf_set_allocator: with torch's caching allocator installed, the operator's
+    arenas and the per-call workspace live in torch's pool, results are unchanged, and
+    freeing the operator hands the bytes back."""
+    c, g, op0, Z = ragged
+    x = _t(c["x"][:, :5])
+    y0 = op0.apply(x).cpu().numpy()
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    hod.use_torch_allocator(True)
+    try:
+        op = hod.Operator(g, tol_con=1e-4, tol_fact=1e-6, precond=hod.P_FP32)
+        torch.cuda.synchronize()
+        held = torch.cuda.memory_allocated() - before
+        st = op.stats()
+        assert held >= st["bytes_fwd"] + st["bytes_pre"]
+        y = op.apply(x).cpu().numpy()
+        assert np.all(_rel(y, y0) <= 1e-6)
+        b = op.plane_wave(c["dirs"][:3])
+        xs, info = op.solve(b, tol=1e-6, use_precond=1)
+        assert info["converged"].all() and np.all(info["relres"] <= 1e-6)
+        op.close()
+        torch.cuda.synchronize()
+        assert torch.cuda.memory_allocated() - before <= held - st["bytes_fwd"]
+    finally:
+        hod.use_torch_allocator(False)
+    # hipMalloc again
+    op2 = hod.Operator(g, tol_con=1e-4)
+    assert np.all(_rel(op2.apply(x).cpu().numpy(), y0) <= 1e-6)
+    op2.close()
