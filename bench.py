@@ -41,6 +41,61 @@ MEASURED_TRAFFIC = {"sources_sha256": "9dbc60c1eb36000551b7affe7da71bb7eb34b1a45
                     "bytes_per_apply": 1317319013.3 + 435986064.0, "launches_per_apply": 10}
 
 
+def measured_copy_gbs(nbytes=1 << 30, reps=10):
+    """Device-to-device copy bandwidth (bytes read + written per second), the STREAM-like
+    reference beside the 8 TB/s specification."""
+    import torch
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / reps
+    del src, dst
+    return 2.0 * nbytes / t / 1e9
+
+
+def stage_roofline(op, st, R, t_fwd):
+    """Roofline summed over the forward apply's stages from the real block dimensions:
+    T_roof = sum_s max(F_s / F_peak, B_s / BW), F_s = 8 R sum m n, B_s = 8 sum m n +
+    8 R (output rows + distinct input rows of the stage).  Stage 0 holds the V0 blocks
+    (each column leaf read once), stage s the level-s transfer blocks (sibling blocks share
+    their input), the last stage the dense leaf blocks and the outer blocks (output: every
+    row once)."""
+    tab = op.export(1, np.int64).reshape(-1, 12)
+    kind, l, oi, lev, a, b, m, n = (tab[:, 0], tab[:, 1], tab[:, 2], tab[:, 5], tab[:, 6],
+                                    tab[:, 7], tab[:, 8], tab[:, 9])
+    stages = []
+    sel = kind == 1
+    stages.append(("V0", sel, float((m[sel]).sum()), float(st["n"])))
+    for s in range(1, int(lev[kind == 2].max(initial=0)) + 1):
+        sel = (kind == 2) & (lev == s)
+        keys = {}
+        for li, oii, ai, bi, ni in zip(l[sel], oi[sel], a[sel], b[sel], n[sel]):
+            keys[(int(li), int(oii), int(ai) >> 1, int(bi))] = int(ni)
+        stages.append((f"W{s}", sel, float(m[sel].sum()), float(sum(keys.values()))))
+    sel = (kind == 0) | (kind == 3)
+    stages.append(("final", sel, float(st["n"]), float(n[sel].sum())))
+    f_peak = PEAK_FP32_MFMA_TFLOPS * 1e12
+    bw = PEAK_HBM_GBS * 1e9
+    t_roof, rows = 0.0, []
+    for name, sel, out_rows, in_rows in stages:
+        ent = float((m[sel] * n[sel]).sum())
+        f = 8.0 * R * ent
+        by = 8.0 * ent + 8.0 * R * (out_rows + in_rows)
+        t = max(f / f_peak, by / bw)
+        t_roof += t
+        rows.append({"stage": name, "gflop": f / 1e9, "mbytes": by / 1e6,
+                     "bound": "mfma" if f / f_peak >= by / bw else "hbm", "t_roof_us": t * 1e6})
+    return {"t_roof_ms": t_roof * 1e3, "t_measured_ms": t_fwd * 1e3, "frac": t_roof / t_fwd,
+            "stages": rows}
+
+
 def sources_sha256():
     import hashlib
     h = hashlib.sha256()
@@ -355,6 +410,9 @@ def main():
         ach = flops_fwd / t_fwd / 1e12
         roof = {"bound": "mfma", "achieved": ach, "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
                 "frac": ach / PEAK_FP32_MFMA_TFLOPS}
+    roof["per_stage"] = stage_roofline(op, st, R, t_fwd)
+    copy_gbs = measured_copy_gbs()
+    roof["measured_peaks"] = {"hbm_copy_gbs": copy_gbs}
     roof.update({"traffic": traffic, "traffic_unit": "bytes per launch",
                  "algorithmic_bytes_per_launch": bytes_fwd / launches,
                  "algorithmic_flops_per_launch": flops_fwd / launches,
