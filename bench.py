@@ -130,6 +130,64 @@ def cpu_baseline_leg(seconds: float) -> dict:
     return dict(seconds=t, steps=k, sec_per_step=t / k)
 
 
+def oracle_mode(args) -> dict:
+    """Times of the oracle (plain numpy/scipy FP64, not a tuned CPU library) on the host:
+    16^3: dense Z, dense product, LU solve, unpreconditioned FGMRES to 1e-6, HOD-BF build
+    (full-row interpolative decompositions, chi 1e-4) and apply; 32^3, 64^3, 128^3:
+    direct-sum rows per second and the FFT-exact product.  Threads: whatever
+    OMP_NUM_THREADS / the BLAS allow (run once with all cores and once with one)."""
+    import platform
+    from oracle import butterfly, gmres, vie
+    from synth import config
+
+    def best(fn, reps):
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t0)
+        return min(ts)
+
+    out = {"mode": "oracle", "threads": os.environ.get("OMP_NUM_THREADS", "unset"),
+           "cpu": platform.processor() or platform.machine(), "host_cpus": os.cpu_count()}
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    out["cpu"] = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    c1 = config("c1_plain_16")
+    g = c1["grid"]
+    b = vie.plane_wave(g, c1["dirs"])[:, 0]
+    t0 = time.perf_counter()
+    Z = vie.dense(g)
+    r = {"n": g.n, "dense_build_s": time.perf_counter() - t0}
+    log(f"[oracle] c1 dense Z built in {r['dense_build_s']:.1f} s")
+    r["dense_matvec_s"] = best(lambda: Z @ b, 5)
+    r["lu_solve_s"] = best(lambda: gmres.lu_solve(Z, b), 2)
+    log(f"[oracle] c1 LU solve {r['lu_solve_s']:.2f} s")
+    t0 = time.perf_counter()
+    _, it, conv, _ = gmres.fgmres(lambda v: Z @ v, b, None, tol=1e-6)
+    r.update(fgmres_s=time.perf_counter() - t0, fgmres_iters=it, fgmres_converged=bool(conv))
+    log(f"[oracle] c1 FGMRES {r['fgmres_s']:.2f} s, {it} steps")
+    t0 = time.perf_counter()
+    H = butterfly.build_hodbf(g, 1e-4)
+    r["hodbf_build_s"] = time.perf_counter() - t0
+    r["hodbf_apply_s"] = best(lambda: H.apply(b), 3)
+    out["c1_plain_16"] = r
+    for name, nrows in (("c2_batched_32", 32), ("c3_sphere_64", 16), ("c5_slabs_128", 4)):
+        cfg = config(name, sample_rows=nrows)
+        g = cfg["grid"]
+        x = vie.plane_wave(g, cfg["dirs"][:1])[:, 0]
+        t_rows = best(lambda: vie.direct_rows(g, x, cfg["rows"]), 1)
+        t_fft = best(lambda: vie.fft_matvec(g, x), 1)
+        out[name] = {"n": g.n, "direct_rows_per_s": nrows / t_rows, "fft_matvec_s": t_fft}
+        log(f"[oracle] {name}: {out[name]}")
+    return out
+
+
 def apply_mode(args, cfg, Operator, P_NONE):
     """Forward operator only: one device copy of known size, then forward applies."""
     import numpy as np
@@ -261,7 +319,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--tol-fact", type=float, default=1e-4)
-    ap.add_argument("--mode", choices=["solve", "apply", "serve", "config"], default="solve")
+    ap.add_argument("--mode", choices=["solve", "apply", "serve", "config", "oracle"],
+                    default="solve")
     ap.add_argument("--config", default="c3_sphere_64", help="workload of --mode config")
     ap.add_argument("--precond-min-level", type=int, default=0)
     ap.add_argument("--restart", type=int, default=20)
@@ -279,6 +338,9 @@ def main():
 
     if args.cpu_baseline_leg:
         print(json.dumps(cpu_baseline_leg(20.0)))
+        return 0
+    if args.mode == "oracle":  # host only, no GPU
+        print(json.dumps(oracle_mode(args)))
         return 0
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
