@@ -290,6 +290,12 @@ static void solve_impl(const hodbf_op &op, int R, const void *b, int64_t ldb, vo
       }
     }
     if (numeric_bad) break;
+    {
+      double worst = 0;
+      for (int k = 0; k < Ra; ++k) worst = std::max(worst, relres[size_t(act[size_t(k)])]);
+      logf("fgmres: %d steps, %d of %d columns still active, worst true residual %.3e", steps,
+           int(std::count(active.begin(), active.end(), 1)), R, worst);
+    }
   }
   launch_scatter(xt, true, x, true, ldx, perm, n, R, st);
   HIPCHK(hipGetLastError());

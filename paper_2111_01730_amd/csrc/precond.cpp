@@ -183,7 +183,7 @@ void build_precond(hodbf_op &op, hipStream_t st) {
   const bool wanth16 = (p.precond_prec & HODBF_P_FP16) != 0;
   // all factor values, each block divided by its largest component magnitude (the
   // pair's load scale), so that the FP16 copy neither overflows nor underflows
-  std::vector<cd> host;
+  std::vector<cf> host;
   pd.scales.clear();
   auto put = [&](const Mat &f, float *scale) -> int64_t {
     const int64_t off = (int64_t(host.size()) + 15) & ~int64_t(15);
@@ -193,7 +193,7 @@ void build_precond(hodbf_op &op, hipStream_t st) {
       mx = std::max({mx, std::abs(double(v.real())), std::abs(double(v.imag()))});
     const float s = mx > 0 ? float(mx) : 1.0f;
     const double inv = 1.0 / double(s);
-    for (size_t e = 0; e < f.v.size(); ++e) host[size_t(off) + e] = cd(f.v[e]) * inv;
+    for (size_t e = 0; e < f.v.size(); ++e) host[size_t(off) + e] = cf(cd(f.v[e]) * inv);
     *scale = s;
     return off;
   };
@@ -313,18 +313,17 @@ void build_precond(hodbf_op &op, hipStream_t st) {
   // arenas
   const size_t count = host.size();
   if (want32) {
-    std::vector<float2> f(count);
-    for (size_t i = 0; i < count; ++i) f[i] = make_float2(float(host[i].real()), float(host[i].imag()));
-    pd.F32.upload(f.data(), count * sizeof(float2), st);
+    static_assert(sizeof(cf) == sizeof(float2), "complex<float> is two floats");
+    pd.F32.upload(host.data(), count * sizeof(float2), st);
   }
   if (wantb16) {
     std::vector<uint32_t> f(count);
-    for (size_t i = 0; i < count; ++i) f[i] = to_bf16_pair(host[i]);
+    for (size_t i = 0; i < count; ++i) f[i] = to_bf16_pair(cd(host[i]));
     pd.BF16.upload(f.data(), count * sizeof(uint32_t), st);
   }
   if (wanth16) {
     std::vector<uint32_t> f(count);
-    for (size_t i = 0; i < count; ++i) f[i] = to_f16_pair(host[i]);
+    for (size_t i = 0; i < count; ++i) f[i] = to_f16_pair(cd(host[i]));
     pd.F16.upload(f.data(), count * sizeof(uint32_t), st);
   }
   const size_t total = op.fwdF.bytes + pd.F32.bytes + pd.BF16.bytes + pd.F16.bytes;
