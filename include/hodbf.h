@@ -124,8 +124,12 @@ hodbf_status hodbf_precond_apply(const hodbf_op *op, int32_t nrhs, hodbf_dtype d
  * layout: complex FP32, tree order (position t holds user index perm[t], see
  * hodbf_export selector 0), right-hand sides interleaved, element (t, q) at
  * ptr[t * nrhs + q].  which: 0 y = Z_con x; 1 y = P x with the default copy;
- * 2 with the FP32 copy; 3 with the BF16 copy; 4 with the FP16 copy.  Only grouped-GEMM kernels run (no
- * permutation), so callers that keep data in tree order avoid two passes.
+ * 2 with the FP32 copy; 3 with the BF16 copy; 4 with the FP16 copy; 5 y = Z_con x and
+ * 6 y = P x (FP32 copy), both with split-BF16 arithmetic: every FP32 factor and input
+ * value is split into BF16 hi + lo parts and each product is hi hi + hi lo + lo hi on
+ * BF16 MFMA with FP32 accumulation (relative error about 2^-17 per product, against
+ * 2^-24 for 0 and 2).  Only grouped-GEMM kernels run (no permutation), so callers that
+ * keep data in tree order avoid two passes.
  * x and y must not overlap.  E_STATE if the requested factors are absent.
  */
 hodbf_status hodbf_apply_tree(const hodbf_op *op, int32_t which, int32_t nrhs, const void *x,
@@ -135,7 +139,9 @@ typedef struct {
   double tol;           /* chi_sol: stop when ||b - Z x|| / ||b|| <= tol per column */
   int32_t restart;      /* GMRES restart length m, 1..200 (20 recommended) */
   int32_t max_iter;     /* cap on Arnoldi steps per column (the paper caps at 3000) */
-  int32_t use_precond;  /* 0: none; 1: operator default; 8 + HODBF_P_FP32 / _BF16 / _FP16 */
+  int32_t use_precond;  /* 0: none; 1: operator default; 8 + HODBF_P_FP32 / _BF16 / _FP16;
+                           16 + HODBF_P_FP32: the FP32 copy with split-BF16 arithmetic
+                           (see hodbf_apply_tree, which 6) */
 } hodbf_solve_opts;
 
 typedef struct {

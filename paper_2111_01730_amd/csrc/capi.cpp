@@ -143,8 +143,8 @@ void run_program(const Program &prog, const void *F, int ftype, const float2 *X,
 int64_t forward_work_rows(const hodbf_op &op) { return op.fwd.t_rows; }
 
 void apply_forward_tree(const hodbf_op &op, const float2 *x, float2 *y, float2 *work, int R,
-                        hipStream_t st) {
-  run_program(op.fwd, op.fwdF.p, FT_C64, x, work, y, R, st);
+                        hipStream_t st, int ftype) {
+  run_program(op.fwd, op.fwdF.p, ftype, x, work, y, R, st);
 }
 
 int64_t precond_work_rows(const hodbf_op &op) {
@@ -354,25 +354,29 @@ hodbf_status hodbf_precond_apply(const hodbf_op *op, int32_t nrhs, hodbf_dtype d
 hodbf_status hodbf_apply_tree(const hodbf_op *op, int32_t which, int32_t nrhs, const void *x,
                               void *y, void *stream) {
   return guarded([&] {
-    if (!op || nrhs < 0 || which < 0 || which > 4) fail(HODBF_E_ARG, "bad operator, nrhs or which");
+    if (!op || nrhs < 0 || which < 0 || which > 6) fail(HODBF_E_ARG, "bad operator, nrhs or which");
     if (nrhs == 0) return;
     if (!x || !y) fail(HODBF_E_ARG, "NULL vector");
     const size_t vb = size_t(op->n) * nrhs * sizeof(float2);
     const char *xb = static_cast<const char *>(x), *yb = static_cast<const char *>(y);
     if (xb < yb + vb && yb < xb + vb) fail(HODBF_E_ARG, "x and y overlap");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    int ft = FT_C64;
-    if (which > 0) {
+    const bool fwd = which == 0 || which == 5;
+    int ft = which == 5 ? FT_C64_S3 : FT_C64;
+    if (!fwd) {
       if (!op->pre.present) fail(HODBF_E_STATE, "operator was built without a preconditioner");
-      ft = which == 1 ? op->pre.default_ft : (which == 2 ? FT_C64 : (which == 3 ? FT_BF16 : FT_F16));
-      if (ft == FT_C64 && !op->pre.F32.p) fail(HODBF_E_STATE, "no FP32 preconditioner copy");
+      ft = which == 1 ? op->pre.default_ft
+                      : (which == 2 ? FT_C64 : (which == 3 ? FT_BF16 : (which == 4 ? FT_F16 : FT_C64_S3)));
+      if ((ft == FT_C64 || ft == FT_C64_S3) && !op->pre.F32.p)
+        fail(HODBF_E_STATE, "no FP32 preconditioner copy");
       if (ft == FT_BF16 && !op->pre.BF16.p) fail(HODBF_E_STATE, "no BF16 preconditioner copy");
       if (ft == FT_F16 && !op->pre.F16.p) fail(HODBF_E_STATE, "no FP16 preconditioner copy");
     }
-    const int64_t rows = which == 0 ? forward_work_rows(*op) : precond_work_rows(*op);
+    const int64_t rows = fwd ? forward_work_rows(*op) : precond_work_rows(*op);
     float2 *wk = static_cast<float2 *>(scratch_alloc(size_t(std::max<int64_t>(rows, 1)) * nrhs * 8, st));
-    if (which == 0)
-      apply_forward_tree(*op, static_cast<const float2 *>(x), static_cast<float2 *>(y), wk, nrhs, st);
+    if (fwd)
+      apply_forward_tree(*op, static_cast<const float2 *>(x), static_cast<float2 *>(y), wk, nrhs, st,
+                         ft);
     else
       apply_precond_tree(*op, ft, static_cast<const float2 *>(x), static_cast<float2 *>(y), wk, nrhs, st);
     HIPCHK(hipGetLastError());

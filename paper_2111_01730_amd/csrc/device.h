@@ -41,9 +41,10 @@ struct EntryJob {
   int32_t r0, m, c_off, n;
 };
 
-// Factor storage: complex FP32; complex BF16 (BF16 MFMA arithmetic); complex FP16
-// (converted to FP32 on load, FP32 MFMA arithmetic).
-enum FactorType { FT_C64 = 0, FT_BF16 = 1, FT_F16 = 2 };
+// Factor storage and arithmetic: complex FP32 (FP32 MFMA); complex BF16 (BF16 MFMA);
+// complex FP16 (converted to FP32 on load, FP32 MFMA); complex FP32 with split-BF16
+// arithmetic (hi + lo BF16 parts, three BF16 MFMA products, FP32 accumulation).
+enum FactorType { FT_C64 = 0, FT_BF16 = 1, FT_F16 = 2, FT_C64_S3 = 3 };
 
 // Grouped GEMM over segs[s0, s0 + ns): OUT(seg rows) = beta * OUT + sum A * in.
 // X, T, OUT: complex FP32 RHS-interleaved (element (row, q) at row * R + q).

@@ -41,6 +41,9 @@ static void solve_impl(const hodbf_op &op, int R, const void *b, int64_t ldb, vo
   } else if (o.use_precond == 8 + HODBF_P_FP32) {
     if (!op.pre.F32.p) fail(HODBF_E_STATE, "no FP32 preconditioner copy");
     pre_ft = FT_C64;
+  } else if (o.use_precond == 16 + HODBF_P_FP32) {
+    if (!op.pre.F32.p) fail(HODBF_E_STATE, "no FP32 preconditioner copy");
+    pre_ft = FT_C64_S3;
   } else if (o.use_precond == 8 + HODBF_P_BF16) {
     if (!op.pre.BF16.p) fail(HODBF_E_STATE, "no BF16 preconditioner copy");
     pre_ft = FT_BF16;

@@ -267,6 +267,73 @@ __device__ __forceinline__ unsigned load_chunk(const ChunkSrc &c, int kb, const 
   return msk;
 }
 
+// The validity mask load_chunk returns, recomputed from the chunk's (uniform) source and
+// first row, so that a caller holding several chunks in flight keeps no mask registers.
+__device__ __forceinline__ unsigned chunk_mask(const ChunkSrc &c, int kb) {
+  const int tid = threadIdx.x;
+  unsigned msk = 0;
+#pragma unroll
+  for (int i = 0; i < kXL; ++i) {
+    const int e = tid + kThreads * i;
+    msk |= unsigned(kb + (e >> 6) < c.n && (e & 63) < c.rc) << i;
+  }
+#pragma unroll
+  for (int i = 0; i < kAL; ++i) {
+    const int e = tid + kThreads * i;
+    msk |= unsigned(kb + e / kTileRows < c.n && e % kTileRows < c.m) << (kXL + i);
+  }
+  return msk;
+}
+
+// Accumulators of one work item into its output rows.  The tile's row map (at most
+// kMaxMapEntries entries, read with uniform loads; the array is padded past its end) is
+// resolved per row in registers; accumulation into the output is a non-returning atomic
+// add (each output element belongs to exactly one item, so it is a plain
+// read-modify-write with nothing to wait on).
+template <int NRI, int NCI, int RW>
+__device__ __forceinline__ void store_item(const Seg &sg, const RowMap *__restrict__ rowmap,
+                                           float2 *__restrict__ OUT, const int R, const int beta,
+                                           const int q0, const int Rc, const int wr, const int wc,
+                                           const floatx4 (&acc)[NRI > 0 ? NRI * NCI : 1]) {
+  constexpr int CW = kWaves / RW;
+  const int lane = threadIdx.x & 63;
+  const int i16 = lane & 15, kk = lane >> 4;
+  const int qo = i16 >> 1, op = i16 & 1;
+  const int ne = sg.map1 - sg.map0;
+  int mstart[kMaxMapEntries], mbase[kMaxMapEntries];
+#pragma unroll
+  for (int k = 0; k < kMaxMapEntries; ++k) {
+    const RowMap e = rowmap[sg.map0 + k];
+    mstart[k] = k < ne ? e.start : kTileRows;
+    mbase[k] = e.out_row - e.start;
+  }
+#pragma unroll
+  for (int ri = 0; ri < NRI; ++ri) {
+    const int rt = wr + ri * RW;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = rt * 16 + 4 * kk + v;
+      int base = mbase[0];
+#pragma unroll
+      for (int k = 1; k < kMaxMapEntries; ++k) base = mstart[k] <= row ? mbase[k] : base;
+      if (row < sg.m) {
+        const int64_t orow = int64_t(base) + row;
+#pragma unroll
+        for (int ci = 0; ci < NCI; ++ci) {
+          const int q = q0 + (wc + ci * CW) * 8 + qo;
+          if (q < q0 + Rc) {
+            float *o = reinterpret_cast<float *>(OUT + orow * R + q) + op;
+            if (beta)
+              unsafeAtomicAdd(o, acc[ri * NCI + ci][v]);
+            else
+              *o = acc[ri * NCI + ci][v];
+          }
+        }
+      }
+    }
+  }
+}
+
 // One work item: tile it / nsl with right-hand-side slice it % nsl of RQ (<= 64) columns.
 // The wave owns NRI row tiles (wr, wr + RW, ...) and NCI column tiles (wc, wc + CW), CW =
 // kWaves / RW; all LDS offsets are compile-time immediates from one lane base address.
@@ -381,45 +448,7 @@ __device__ __forceinline__ void tile_item(const int it, const int nsl, const int
     }
     if (last) break;
   }
-  {
-    // the tile's row map (at most kMaxMapEntries entries, read with uniform loads;
-    // the array is padded past its end) resolved per row in registers; accumulation
-    // into the output is a non-returning atomic add (each output element belongs to
-    // exactly one item, so it is a plain read-modify-write with nothing to wait on)
-    const int ne = sg.map1 - sg.map0;
-    int mstart[kMaxMapEntries], mbase[kMaxMapEntries];
-#pragma unroll
-    for (int k = 0; k < kMaxMapEntries; ++k) {
-      const RowMap e = rowmap[sg.map0 + k];
-      mstart[k] = k < ne ? e.start : kTileRows;
-      mbase[k] = e.out_row - e.start;
-    }
-#pragma unroll
-    for (int ri = 0; ri < NRI; ++ri) {
-      const int rt = wr + ri * RW;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = rt * 16 + 4 * kk + v;
-        int base = mbase[0];
-#pragma unroll
-        for (int k = 1; k < kMaxMapEntries; ++k) base = mstart[k] <= row ? mbase[k] : base;
-        if (row < sg.m) {
-          const int64_t orow = int64_t(base) + row;
-#pragma unroll
-          for (int ci = 0; ci < NCI; ++ci) {
-            const int q = q0 + (wc + ci * CW) * 8 + qo;
-            if (q < q0 + Rc) {
-              float *o = reinterpret_cast<float *>(OUT + orow * R + q) + op;
-              if (beta)
-                unsafeAtomicAdd(o, acc[ri * NCI + ci][v]);
-              else
-                *o = acc[ri * NCI + ci][v];
-            }
-          }
-        }
-      }
-    }
-  }
+  store_item<NRI, NCI, RW>(sg, rowmap, OUT, R, beta, q0, Rc, wr, wc, acc);
 }
 
 // Work index of this workgroup.  Blocks are dealt to the kNumXcd XCDs round-robin; here
@@ -443,6 +472,54 @@ struct TileClasses {
   int seg0[kWaves + 1];
 };
 
+// The waves of a workgroup as a cw x rw grid for a tile of nrt row tiles: short tiles
+// spread over column tiles, tall tiles over row tiles too; every wave then owns at most
+// 4 row tiles x 2 column tiles.  sel = 2 nri + nci - 1 (0: no tiles) is wave-uniform.
+struct WaveGrid {
+  int rw, wr, wc, sel;
+};
+__device__ __forceinline__ WaveGrid wave_grid(int wave, int nrt, int R, int RQ) {
+  const int nnt = ((R < RQ ? R : RQ) + 7) >> 3;  // column tiles of a full slice
+  const int nntp = nnt >= 8 ? 8 : (nnt >= 4 ? 4 : (nnt >= 2 ? 2 : 1));
+  const int cw = (kWaves == 8 && nrt > 2) || nntp > kWaves ? (nntp > 4 ? 4 : nntp) : nntp;
+  WaveGrid g;
+  g.rw = kWaves / cw;
+  g.wc = wave % cw;
+  g.wr = wave / cw;
+  // row tiles wr, wr + rw, ... below nrt; column tiles wc, wc + cw below nnt (<= 2)
+  const int nri = g.wr < nrt ? (nrt - g.wr + g.rw - 1) / g.rw : 0;
+  const int nci = g.wc < nnt ? (g.wc + cw < nnt ? 2 : 1) : 0;
+  g.sel = nci == 0 ? 0 : nri * 2 + (nci - 1);
+  return g;
+}
+
+// One instantiation of HODBF_CLASS(row tiles, column tiles, wave rows) per wave shape.
+#define HODBF_DISPATCH_CLASSES(g)                 \
+  if ((g).rw == 1) {                              \
+    switch ((g).sel) {                            \
+      case 2: HODBF_CLASS(1, 1, 1); break;        \
+      case 3: HODBF_CLASS(1, 2, 1); break;        \
+      case 4: HODBF_CLASS(2, 1, 1); break;        \
+      case 5: HODBF_CLASS(2, 2, 1); break;        \
+      case 6: HODBF_CLASS(3, 1, 1); break;        \
+      case 7: HODBF_CLASS(3, 2, 1); break;        \
+      case 8: HODBF_CLASS(4, 1, 1); break;        \
+      case 9: HODBF_CLASS(4, 2, 1); break;        \
+      default: HODBF_CLASS(0, 1, 1); break;       \
+    }                                             \
+  } else if ((g).rw == 2) {                       \
+    switch ((g).sel) {                            \
+      case 2: HODBF_CLASS(1, 1, 2); break;        \
+      case 3: HODBF_CLASS(1, 2, 2); break;        \
+      case 4: HODBF_CLASS(2, 1, 2); break;        \
+      case 5: HODBF_CLASS(2, 2, 2); break;        \
+      default: HODBF_CLASS(0, 1, 2); break;       \
+    }                                             \
+  } else {                                        \
+    if ((g).sel == 2) HODBF_CLASS(1, 1, 4);       \
+    else HODBF_CLASS(0, 1, 4);                    \
+  }
+
 template <typename FT>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_grouped_mfma_f32(
     const Seg *__restrict__ segs, const Pair *__restrict__ pairs, const RowMap *__restrict__ rowmap,
@@ -456,45 +533,198 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
   int c = 0;
   while (c < kWaves - 1 && it >= tc.seg0[c + 1] * nsl) ++c;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int nrt = c + 1;
-  const int nnt = ((R < RQ ? R : RQ) + 7) >> 3;  // column tiles of a full slice
-  // the waves as a cw x rw grid: short tiles spread over column tiles, tall tiles
-  // over row tiles too; every wave then owns at most 4 row tiles x 2 column tiles
-  const int nntp = nnt >= 8 ? 8 : (nnt >= 4 ? 4 : (nnt >= 2 ? 2 : 1));
-  const int cw = (kWaves == 8 && nrt > 2) || nntp > kWaves ? (nntp > 4 ? 4 : nntp) : nntp;
-  const int rw = kWaves / cw;  // wave rows
-  const int wc = wave % cw, wr = wave / cw;
-  // row tiles wr, wr + rw, ... below nrt; column tiles wc, wc + cw below nnt (<= 2)
-  const int nri = wr < nrt ? (nrt - wr + rw - 1) / rw : 0;
-  const int nci = wc < nnt ? (wc + cw < nnt ? 2 : 1) : 0;
-  const int sel = nci == 0 ? 0 : nri * 2 + (nci - 1);  // wave-uniform
+  const WaveGrid wg = wave_grid(wave, c + 1, R, RQ);
 #define HODBF_CLASS(NR, NC, RWV)                                                             \
-  tile_item<FT, NR, NC, RWV>(it, nsl, RQ, segs, pairs, rowmap, F, X, T, OUT, R, beta, wr, wc, xs, \
-                             as)
-  if (rw == 1) {
-    switch (sel) {
-      case 2: HODBF_CLASS(1, 1, 1); break;
-      case 3: HODBF_CLASS(1, 2, 1); break;
-      case 4: HODBF_CLASS(2, 1, 1); break;
-      case 5: HODBF_CLASS(2, 2, 1); break;
-      case 6: HODBF_CLASS(3, 1, 1); break;
-      case 7: HODBF_CLASS(3, 2, 1); break;
-      case 8: HODBF_CLASS(4, 1, 1); break;
-      case 9: HODBF_CLASS(4, 2, 1); break;
-      default: HODBF_CLASS(0, 1, 1); break;  // no tiles: loads and barriers only
+  tile_item<FT, NR, NC, RWV>(it, nsl, RQ, segs, pairs, rowmap, F, X, T, OUT, R, beta, wg.wr, \
+                             wg.wc, xs, as)
+  HODBF_DISPATCH_CLASSES(wg)
+#undef HODBF_CLASS
+}
+
+// Split-BF16 arithmetic for complex FP32 factors and inputs.  Each FP32 value v is
+// written as hi + lo with hi = bf16(v) and lo = bf16(v - hi), both rounded to nearest
+// even, so |v - hi - lo| <= 2^-18 |v|; a product a x is taken as
+// hi_a hi_x + hi_a lo_x + lo_a hi_x (the dropped lo_a lo_x is below 2^-17 |a x|) on
+// v_mfma_f32_16x16x32_bf16 with FP32 accumulation.  One MFMA consumes a whole chunk of
+// 16 complex columns (32 real K), against eight FP32 16x16x4 MFMAs of four times the
+// cycles each: the same tiles, work items and chunk pipeline as tile_item, with the
+// chunk split into hi / lo once, when it is written to LDS.
+//
+// Lane l = 16 kk + i16 supplies K slots 8 kk .. 8 kk + 7 of row / column i16 (the two
+// operands use the same slot order, so the sum over K needs no particular hardware slot
+// order).  Slots 2 v, 2 v + 1 are (Re, Im) of complex column 4 kk + v: for the factor
+// that is the stored pair itself, for the input of output column 2 q it is (xr, -xi) and
+// of column 2 q + 1 it is (xi, xr).  LDS holds the factor chunk row-major and the input
+// chunk column-major in both forms, each complex value as (hi pair, lo pair), so a
+// fragment is two 16-byte reads.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+typedef float floatx2v __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kS3 = kKC + 2;  // LDS stride (uint2) of a factor row / an input column
+
+// (hi pair, lo pair) of the complex value (re, im), each packed re | im << 16
+__device__ __forceinline__ uint2 split_bf16(float re, float im) {
+  const floatx2v v = {re, im};
+  const uint32_t hb = __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2v));
+  const float hre = __uint_as_float(hb << 16), him = __uint_as_float(hb & 0xFFFF0000u);
+  const floatx2v r = {re - hre, im - him};
+  const uint32_t lb = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, bf16x2v));
+  return make_uint2(hb, lb);
+}
+
+template <int NRI, int NCI, int RW>
+__device__ __forceinline__ void tile_item_s3(const int it, const int nsl, const int RQ,
+                                             const Seg *__restrict__ segs,
+                                             const Pair *__restrict__ pairs,
+                                             const RowMap *__restrict__ rowmap,
+                                             const float2 *__restrict__ F,
+                                             const float2 *__restrict__ X,
+                                             const float2 *__restrict__ T,
+                                             float2 *__restrict__ OUT, const int R,
+                                             const int beta, const int wr, const int wc,
+                                             uint2 *as, uint2 *xs) {
+  constexpr int CW = kWaves / RW;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int i16 = lane & 15;
+  const int kk = lane >> 4;
+  const int qo = i16 >> 1, op = i16 & 1;
+  // this lane's fragment bases: factor row wr * 16 + i16, input column (wc * 8 + qo) of form op
+  const uint2 *al = as + (wr * 16 + i16) * kS3 + 4 * kk;
+  const uint2 *xl = xs + op * (64 * kS3) + (wc * 8 + qo) * kS3 + 4 * kk;
+  const Seg sg = segs[it / nsl];
+  const int q0 = (it % nsl) * RQ;
+  const int Rc = min(R - q0, RQ);
+  floatx4 acc[NRI > 0 ? NRI * NCI : 1];
+#pragma unroll
+  for (int j = 0; j < (NRI > 0 ? NRI * NCI : 1); ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  // The load cursor (pair p, column k0, source cur) runs two chunks ahead of the chunk
+  // being multiplied: two register sets alternate.  Past the tile's last chunk the cursor
+  // stays on it and the loads repeat it (in bounds, never used), so every iteration
+  // issues the same loads and each LDS write waits only for its own set.
+  ChunkSrc cur = chunk_src(sg.first, R, q0, Rc, sg.m);
+  int p = sg.p0, k0 = 0;
+  bool done = false;
+  Pair pr1;  // descriptor of pair p + 1
+  if (p + 1 < sg.p1) pr1 = pairs[p + 1];
+  auto advance = [&]() {
+    if (k0 + kKC < cur.n) {
+      k0 += kKC;
+    } else if (p + 1 < sg.p1) {
+      ++p;
+      k0 = 0;
+      cur = chunk_src(pr1, R, q0, Rc, sg.m);
+      if (p + 1 < sg.p1) pr1 = pairs[p + 1];
+    } else {
+      done = true;
     }
-  } else if (rw == 2) {
-    switch (sel) {
-      case 2: HODBF_CLASS(1, 1, 2); break;
-      case 3: HODBF_CLASS(1, 2, 2); break;
-      case 4: HODBF_CLASS(2, 1, 2); break;
-      case 5: HODBF_CLASS(2, 2, 2); break;
-      default: HODBF_CLASS(0, 1, 2); break;
+  };
+  auto write_chunk = [&](const float2 (&xr)[kXL], const float2 (&ar)[kAL], unsigned msk,
+                         float lscale) {
+#pragma unroll
+    for (int i = 0; i < kXL; ++i) {
+      const int e = tid + kThreads * i;
+      const bool ok = (msk >> i) & 1u;
+      const uint2 h = split_bf16(ok ? xr[i].x : 0.f, ok ? xr[i].y : 0.f);
+      const int c = e >> 6, q = e & 63;
+      // form 0: (xr, -xi); form 1: (xi, xr)
+      xs[q * kS3 + c] = make_uint2(h.x ^ 0x80000000u, h.y ^ 0x80000000u);
+      xs[64 * kS3 + q * kS3 + c] = make_uint2(__builtin_amdgcn_alignbit(h.x, h.x, 16),
+                                              __builtin_amdgcn_alignbit(h.y, h.y, 16));
     }
-  } else {
-    if (sel == 2) HODBF_CLASS(1, 1, 4);
-    else HODBF_CLASS(0, 1, 4);
+#pragma unroll
+    for (int i = 0; i < kAL; ++i) {
+      const int e = tid + kThreads * i;
+      const bool ok = (msk >> (kXL + i)) & 1u;
+      as[(e % kTileRows) * kS3 + e / kTileRows] =
+          split_bf16(ok ? ar[i].x * lscale : 0.f, ok ? ar[i].y * lscale : 0.f);
+    }
+  };
+  auto multiply = [&]() {
+    if (NRI > 0) {
+      bf16x8 xh[NCI], xo[NCI];
+#pragma unroll
+      for (int ci = 0; ci < NCI; ++ci) {
+        const u32x4 *b = reinterpret_cast<const u32x4 *>(xl + ci * CW * 8 * kS3);
+        const u32x4 b0 = b[0], b1 = b[1];  // (hi, lo) of complex columns 4 kk .. 4 kk + 3
+        xh[ci] = __builtin_bit_cast(bf16x8, u32x4{b0.x, b0.z, b1.x, b1.z});
+        xo[ci] = __builtin_bit_cast(bf16x8, u32x4{b0.y, b0.w, b1.y, b1.w});
+      }
+      // one row tile at a time (its fragments are used by NCI column tiles); within it the
+      // three products run term-major, so consecutive MFMAs alternate accumulators
+#pragma unroll
+      for (int ri = 0; ri < NRI; ++ri) {
+        const u32x4 *a = reinterpret_cast<const u32x4 *>(al + ri * RW * 16 * kS3);
+        const u32x4 a0 = a[0], a1 = a[1];
+        const bf16x8 ah = __builtin_bit_cast(bf16x8, u32x4{a0.x, a0.z, a1.x, a1.z});
+        const bf16x8 ao = __builtin_bit_cast(bf16x8, u32x4{a0.y, a0.w, a1.y, a1.w});
+#pragma unroll
+        for (int ci = 0; ci < NCI; ++ci)
+          acc[ri * NCI + ci] =
+              __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, xh[ci], acc[ri * NCI + ci], 0, 0, 0);
+#pragma unroll
+        for (int ci = 0; ci < NCI; ++ci)
+          acc[ri * NCI + ci] =
+              __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, xo[ci], acc[ri * NCI + ci], 0, 0, 0);
+#pragma unroll
+        for (int ci = 0; ci < NCI; ++ci)
+          acc[ri * NCI + ci] =
+              __builtin_amdgcn_mfma_f32_16x16x32_bf16(ao, xh[ci], acc[ri * NCI + ci], 0, 0, 0);
+      }
+    }
+  };
+  // each set keeps its chunk's uniform source and first column; the lane masks are
+  // recomputed from them when the set is written to LDS
+  float2 xr0[kXL], ar0[kAL], xr1[kXL], ar1[kAL];
+  ChunkSrc c0 = cur, c1;
+  int kb0 = k0, kb1;
+  (void)load_chunk<float2>(cur, k0, F, X, T, R, xr0, ar0);
+  advance();
+  bool v1 = !done;  // set 1 holds a chunk of the tile
+  c1 = cur;
+  kb1 = k0;
+  (void)load_chunk<float2>(cur, k0, F, X, T, R, xr1, ar1);
+  while (true) {
+    __syncthreads();  // previous chunk fully consumed
+    write_chunk(xr0, ar0, chunk_mask(c0, kb0), c0.scale);
+    __syncthreads();
+    advance();
+    const bool v0 = !done;  // set 0 gets the chunk after set 1's
+    c0 = cur;
+    kb0 = k0;
+    (void)load_chunk<float2>(cur, k0, F, X, T, R, xr0, ar0);
+    multiply();
+    if (!v1) break;
+    __syncthreads();
+    write_chunk(xr1, ar1, chunk_mask(c1, kb1), c1.scale);
+    __syncthreads();
+    advance();
+    v1 = !done;
+    c1 = cur;
+    kb1 = k0;
+    (void)load_chunk<float2>(cur, k0, F, X, T, R, xr1, ar1);
+    multiply();
+    if (!v0) break;
   }
+  store_item<NRI, NCI, RW>(sg, rowmap, OUT, R, beta, q0, Rc, wr, wc, acc);
+}
+
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_grouped_mfma_s3(
+    const Seg *__restrict__ segs, const Pair *__restrict__ pairs, const RowMap *__restrict__ rowmap,
+    const float2 *__restrict__ F, const float2 *__restrict__ X, const float2 *__restrict__ T,
+    float2 *__restrict__ OUT, int R, int beta, int RQ, int nsl, TileClasses tc) {
+  __shared__ __attribute__((aligned(16))) uint2 as[kTileRows * kS3];
+  __shared__ __attribute__((aligned(16))) uint2 xs[2 * 64 * kS3];
+  const int it = xcd_work_index();
+  if (it >= tc.seg0[kWaves] * nsl) return;
+  int c = 0;
+  while (c < kWaves - 1 && it >= tc.seg0[c + 1] * nsl) ++c;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const WaveGrid wg = wave_grid(wave, c + 1, R, RQ);
+#define HODBF_CLASS(NR, NC, RWV)                                                              \
+  tile_item_s3<NR, NC, RWV>(it, nsl, RQ, segs, pairs, rowmap, F, X, T, OUT, R, beta, wg.wr, wg.wc, \
+                            as, xs)
+  HODBF_DISPATCH_CLASSES(wg)
 #undef HODBF_CLASS
 }
 
@@ -634,6 +864,9 @@ void launch_grouped(const Seg *segs, const Pair *pairs, const RowMap *rowmap, in
   const dim3 grid{unsigned((items + gq - 1) / gq * gq)};
   if (ftype == FT_C64)
     hipLaunchKernelGGL(k_grouped_mfma_f32<float2>, grid, dim3(kThreads), 0, st, sp, pairs, rowmap,
+                       static_cast<const float2 *>(F), X, T, OUT, R, beta, RQ, nsl, tc);
+  else if (ftype == FT_C64_S3)
+    hipLaunchKernelGGL(k_grouped_mfma_s3, grid, dim3(kThreads), 0, st, sp, pairs, rowmap,
                        static_cast<const float2 *>(F), X, T, OUT, R, beta, RQ, nsl, tc);
   else
     hipLaunchKernelGGL(k_grouped_mfma_f32<FF16>, grid, dim3(kThreads), 0, st, sp, pairs, rowmap,

@@ -129,8 +129,9 @@ void run_program(const Program &prog, const void *F, int ftype, const float2 *X,
                  float2 *OUT, int R, hipStream_t st);
 
 // y_tree = Z_con x_tree and z_tree = P x_tree on internal buffers (workspace supplied).
+// ftype FT_C64 (FP32 arithmetic) or FT_C64_S3 (split-BF16 arithmetic) for the forward.
 void apply_forward_tree(const hodbf_op &op, const float2 *x, float2 *y, float2 *work, int R,
-                        hipStream_t st);
+                        hipStream_t st, int ftype = FT_C64);
 int64_t forward_work_rows(const hodbf_op &op);
 void apply_precond_tree(const hodbf_op &op, int ftype, const float2 *x, float2 *z, float2 *work,
                         int R, hipStream_t st);

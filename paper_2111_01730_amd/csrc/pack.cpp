@@ -307,6 +307,22 @@ void upload_program(Program &prog, PackSink &pk, hipStream_t st) {
     for (int c = 0; c <= kRowClasses; ++c)
       ln.cls[c] = std::lower_bound(b, e, c + 1, [&](const Seg &sg, int v) { return nrt(sg) < v; }) - b;
   }
+  // per-launch shape summary (tiles, rows, chunks of 16 columns per tile) for the log
+  for (size_t li = 0; li < pk.launches.size(); ++li) {
+    const Launch &ln = pk.launches[li];
+    int64_t rows = 0, chunks = 0, cmax = 0;
+    for (int64_t s = ln.s0; s < ln.s0 + ln.ns; ++s) {
+      const Seg &sg = pk.segs[size_t(s)];
+      int64_t c = 0;
+      for (int32_t p = sg.p0; p < sg.p1; ++p) c += (pk.pairs[size_t(p)].n + 15) / 16;
+      rows += sg.m;
+      chunks += c;
+      cmax = std::max(cmax, c);
+    }
+    logf("  launch %zu: %lld tiles, %.1f rows and %.1f chunks per tile, longest %lld chunks", li,
+         (long long)ln.ns, ln.ns ? double(rows) / double(ln.ns) : 0.0,
+         ln.ns ? double(chunks) / double(ln.ns) : 0.0, (long long)cmax);
+  }
   prog.launches = pk.launches;
   prog.t_rows = pk.t_rows;
   prog.nseg = int64_t(pk.segs.size());

@@ -102,7 +102,8 @@ class Operator:
     def apply_tree(self, x: torch.Tensor, which: int = 0) -> torch.Tensor:
         """Products on internal-layout vectors: x of shape (N, R) complex64 in tree order
         (row t = user index perm[t]), contiguous, so element (t, q) sits at t*R + q.
-        which: 0 Z_con, 1 P (default copy), 2 P FP32 copy, 3 P BF16 copy, 4 P FP16 copy."""
+        which: 0 Z_con, 1 P (default copy), 2 P FP32 copy, 3 P BF16 copy, 4 P FP16 copy,
+        5 Z_con and 6 P FP32 copy with split-BF16 arithmetic."""
         if x.dtype != torch.complex64 or not x.is_contiguous() or x.dim() != 2:
             raise ValueError("x must be a contiguous (N, R) complex64 tensor")
         y = torch.empty_like(x)
@@ -121,13 +122,15 @@ class Operator:
     def solve(self, b: torch.Tensor, tol=1e-4, restart=20, max_iter=3000, use_precond=1):
         """x ~ Z^{-1} b by right-preconditioned FGMRES; returns (x, info dict).
 
-        use_precond: 0 none, 1 the operator's default copy, 'fp32', 'bf16' or 'fp16'.
+        use_precond: 0 none, 1 the operator's default copy, 'fp32', 'bf16' or 'fp16', or
+        'fp32_split' (the FP32 copy with split-BF16 arithmetic).
         """
         if b.dtype != torch.complex128:
             raise ValueError("b must be complex128")
         bc, R = _as_cols(b, self.n)
         x = torch.empty_like(bc)
-        up = {"fp32": 8 + P_FP32, "bf16": 8 + P_BF16, "fp16": 8 + P_FP16}.get(use_precond, use_precond)
+        up = {"fp32": 8 + P_FP32, "bf16": 8 + P_BF16, "fp16": 8 + P_FP16,
+              "fp32_split": 16 + P_FP32}.get(use_precond, use_precond)
         opts = _lib.SolveOpts(tol=tol, restart=restart, max_iter=max_iter, use_precond=int(up))
         iters = np.zeros(R, dtype=np.int32)
         conv = np.zeros(R, dtype=np.int32)

@@ -57,6 +57,36 @@ def test_apply_arithmetic_parity_with_exported_factors(ragged, R):
     assert np.all(_rel(y, ref.apply(xr)) <= 2e-5)
 
 
+# Split-BF16 arithmetic (apply_tree which 5): every FP32 value v = hi + lo with
+# |v - hi - lo| <= 2^-18 |v|, and hi hi + hi lo + lo hi drops lo lo (<= 2^-18 |a x|), so
+# one product carries a relative error of at most 3 * 2^-18 of |a| |x|.  A column passes
+# through at most L_H + 2 dependent products (V^0, W^1..W^L, the final block; the leaf
+# block runs beside them), so the normwise bound is (L_H + 2) * 3 * 2^-18 ~ 8e-5 at
+# L_H = 5 when the products do not cancel; the test allows twice that.
+S3_FWD_TOL = 2 * (5 + 2) * 3 * 2.0**-18
+
+
+@pytest.mark.parametrize("R", [1, 5, 64, 70])
+def test_split_bf16_apply_parity_with_exported_factors(ragged, R):
+    from tests.plan_tools import hodbf_from_export
+    c, g, op, Z = ragged
+    assert op.stats()["levels"] <= 5
+    table, vals = op.forward_blocks()
+    ref = hodbf_from_export(g, op.perm(), table, vals)
+    x = c["x"][:, :R].astype(np.complex64).astype(np.complex128)
+    perm = torch.as_tensor(op.perm().astype(np.int64), device="cuda")
+    xt = _t(x, torch.complex64)[perm].contiguous()
+    yt = op.apply_tree(xt, 5)
+    y = torch.empty_like(yt)
+    y[perm] = yt
+    y = y.cpu().numpy().astype(np.complex128)
+    err = _rel(y, ref.apply(x))
+    print(f"[split-BF16 forward R={R}: max rel err {err.max():.2e}]", flush=True)
+    assert np.all(err <= S3_FWD_TOL), err
+    # and it is the same operator as the FP32 path to well inside the compression tolerance
+    assert np.all(_rel(y, Z @ x) <= 1e-3)
+
+
 def test_entry_generation_matches_oracle(ragged):
     c, g, op, Z = ragged
     table, vals = op.forward_blocks()

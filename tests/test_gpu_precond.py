@@ -42,7 +42,10 @@ def case():
     return c, g, op, vie.dense(g)
 
 
-@pytest.mark.parametrize("copy,which,tol", [("fp32", 2, 2e-5), ("fp16", 4, 2e-5), ("bf16", 3, 2e-2)])
+# which 6: the FP32 copy with split-BF16 arithmetic, 2^-17-class rounding per product
+# against FP32's 2^-24, i.e. 128 x the FP32 tolerance
+@pytest.mark.parametrize("copy,which,tol", [("fp32", 2, 2e-5), ("fp16", 4, 2e-5), ("bf16", 3, 2e-2),
+                                            ("fp32", 6, 128 * 2e-5)])
 @pytest.mark.parametrize("R", [1, 8])
 def test_precond_apply_matches_exported_factors(case, copy, which, tol, R):
     # the oracle re-applies the GPU's stored factors (values as stored, block scales
@@ -54,6 +57,8 @@ def test_precond_apply_matches_exported_factors(case, copy, which, tol, R):
     ref = precond_from_export(g, op.perm(), table, vals, op.stats()["levels"])
     x = c["x"][:, :R].astype(np.complex64).astype(np.complex128)
     z = _apply_copy(op, x, which)
+    print(f"[precond copy {copy} which {which} R={R}: max rel err "
+          f"{_rel(z, ref.apply(x)).max():.2e}]", flush=True)
     assert np.all(_rel(z, ref.apply(x)) <= tol), _rel(z, ref.apply(x))
     if copy == "fp32":
         assert np.all(_rel(Z @ ref.apply(x), x) <= 0.3)  # the factors form an approximate inverse
@@ -86,13 +91,15 @@ def test_preconditioned_solve_iterations_and_residual(case):
     b = op.plane_wave(c["dirs"])
     bn = b.cpu().numpy()
     out = {}
-    for mode in ("fp16", "fp32", 0):
+    for mode in ("fp16", "fp32", "fp32_split", 0):
         x, info = op.solve(b, tol=1e-5, restart=20, max_iter=500, use_precond=mode)
         assert info["converged"].all(), (mode, info)
         xn = x.cpu().numpy()
         assert np.all(_rel(Z @ xn, bn) <= 1e-5 + 1e-3)  # chi_sol + compression error
         out[mode] = info["iters"]
     assert out["fp16"].max() <= 15 and out["fp32"].max() <= 15
+    # split-BF16 arithmetic on the FP32 copy preconditions as well as FP32 arithmetic
+    assert np.abs(out["fp32_split"].astype(int) - out["fp32"].astype(int)).max() <= 1
     assert out[0].min() > 2 * out["fp32"].max()
     # the oracle's preconditioner at the same chi_fact needs a comparable count
     po = oprecond.build_precond(g, 1e-2)
