@@ -34,11 +34,13 @@ WORKLOAD = "c2_batched_32"
 TOL_SOL = 1e-4
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
-# HBM bytes of one forward apply of this workload, from the FETCH_SIZE / WRITE_SIZE
-# counter runs recorded in profiles/grouped_mfma_f32_forward_c2_r64_traffic.md (scaled
-# by a 256 MiB copy); valid only while the kernel and packing sources are unchanged.
-MEASURED_TRAFFIC = {"sources_sha256": "9dbc60c1eb36000551b7affe7da71bb7eb34b1a4515dce2b19d53d05b729f193",
-                    "bytes_per_apply": 1317319013.3 + 435986064.0, "launches_per_apply": 10}
+PEAK_BF16_MFMA_TFLOPS = 2500.0
+# HBM bytes of one apply of this workload (R = 64) per kernel, from the FETCH_SIZE /
+# WRITE_SIZE counter runs recorded in profiles/*_traffic.md (scaled by a 256 MiB copy);
+# valid only while the kernel and packing sources hash to sources_sha256.
+MEASURED_TRAFFIC = {"sources_sha256": "",
+                    "precond_s3": {"bytes_per_apply": None, "launches_per_apply": 55},
+                    "forward_f32": {"bytes_per_apply": None, "launches_per_apply": 10}}
 
 
 def measured_copy_gbs(nbytes=1 << 30, reps=10):
@@ -189,12 +191,21 @@ def oracle_mode(args) -> dict:
 
 
 def apply_mode(args, cfg, Operator, P_NONE):
-    """Forward operator only: one device copy of known size, then forward applies."""
+    """Applies only (--which 0: the forward operator; 6: the preconditioner's FP32 copy on
+    split-BF16 arithmetic, the mixed solve's form): one device copy of known size, then
+    applies."""
     import numpy as np
     import torch
+
+    from paper_2111_01730_amd.hodbf import P_FP32
     g = cfg["grid"]
     R = cfg["nrhs"]
-    op = Operator(g, tol_con=cfg["tol"], precond=P_NONE, seed=cfg["seed"])
+    which = args.which
+    if which not in (0, 2, 5, 6):
+        raise SystemExit("--which must be 0, 2, 5 or 6")
+    pre = which in (2, 6)
+    op = Operator(g, tol_con=cfg["tol"], tol_fact=args.tol_fact if pre else 0.0,
+                  precond=P_FP32 if pre else P_NONE, seed=cfg["seed"])
     st = op.stats()
     b = op.plane_wave(cfg["dirs"])
     perm = torch.as_tensor(op.perm().astype(np.int64), device="cuda")
@@ -206,19 +217,22 @@ def apply_mode(args, cfg, Operator, P_NONE):
     torch.cuda.synchronize()
     reps = max(1, args.steps)
     for _ in range(args.warmup):
-        op.apply_tree(xt, 0)
+        op.apply_tree(xt, which)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(reps):
-        op.apply_tree(xt, 0)
+        op.apply_tree(xt, which)
     e1.record(stream)
     torch.cuda.synchronize()
     t = e0.elapsed_time(e1) / reps * 1e-3
-    fl = 8.0 * R * st["entries_fwd"]
-    print(json.dumps({"mode": "apply", "apply_ms": t * 1e3, "apply_gflops": fl / t / 1e9,
-                      "launches_per_apply": st["fwd_stages"], "entries_fwd": st["entries_fwd"],
+    ent = st["entries_pre"] if pre else st["entries_fwd"]
+    fl = 8.0 * R * ent
+    print(json.dumps({"mode": "apply", "which": which, "apply_ms": t * 1e3,
+                      "apply_gflops": fl / t / 1e9,
+                      "launches_per_apply": st["pre_stages"] if pre else st["fwd_stages"],
+                      "entries": ent, "io_rows": st["io_rows_pre"] if pre else st["io_rows_fwd"],
                       "reps": reps, "copy_bytes": ref.numel() * 4}), flush=True)
     return 0
 
@@ -334,6 +348,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-baseline-leg", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--apply-reps", type=int, default=20)
+    ap.add_argument("--which", type=int, default=0,
+                    help="--mode apply: 0 forward, 6 preconditioner on split-BF16 arithmetic")
     args = ap.parse_args()
 
     if args.cpu_baseline_leg:
@@ -387,34 +403,38 @@ def main():
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps * 1e-3
 
+    # the mixed form: FP32 forward on FP32 MFMA, the preconditioner's FP32 copy on
+    # split-BF16 MFMA with FP32 accumulation, FP64 Krylov; R columns batched
+    MIXED = "fp32_split"
     t_fwd = time_apply(0, args.apply_reps)
-    t_pre = {c: time_apply(w, args.apply_reps) for c, w in (("fp32", 2), ("fp16", 4), ("bf16", 3))}
+    t_pre = {c: time_apply(w, args.apply_reps)
+             for c, w in ((MIXED, 6), ("fp32", 2), ("fp16", 4), ("bf16", 3))}
     flops_fwd = 8.0 * R * st["entries_fwd"]
     log(f"[apply] fwd {t_fwd * 1e3:.3f} ms ({flops_fwd / t_fwd / 1e9:.1f} GFLOP/s), precond "
         + ", ".join(f"{c} {t * 1e3:.3f} ms" for c, t in t_pre.items()))
 
     # warmup solves
     for _ in range(args.warmup):
-        _, info = op.solve(b, tol=TOL_SOL, use_precond="fp32")
+        _, info = op.solve(b, tol=TOL_SOL, use_precond=MIXED)
     torch.cuda.synchronize()
     iters = []
     conv = True
     torch.cuda.synchronize()
     ts = time.perf_counter()
     for _ in range(args.steps):
-        x, info = op.solve(b, tol=TOL_SOL, use_precond="fp32")
+        x, info = op.solve(b, tol=TOL_SOL, use_precond=MIXED)
         iters.append(int(info["iters"].max()))
         conv = conv and bool(info["converged"].all())
     torch.cuda.synchronize()
     t_step = (time.perf_counter() - ts) / args.steps
     solves_per_s = R / t_step
     iters_mean = float(info["iters"].mean())
-    log(f"[solve batched fp32] {t_step * 1e3:.1f} ms/step, iters max {iters}, mean {iters_mean:.1f}, "
-        f"converged {conv}, relres max {info['relres'].max():.2e}")
+    log(f"[solve batched {MIXED}] {t_step * 1e3:.1f} ms/step, iters max {iters}, "
+        f"mean {iters_mean:.1f}, converged {conv}, relres max {info['relres'].max():.2e}")
 
-    # the reduced-precision preconditioner copies on the same batch (bounded)
+    # the other preconditioner arithmetics on the same batch (bounded)
     variants = {}
-    for c in ("fp16", "bf16"):
+    for c in ("fp32", "fp16", "bf16"):
         torch.cuda.synchronize()
         tv = time.perf_counter()
         _, vi = op.solve(b, tol=TOL_SOL, use_precond=c, max_iter=args.variant_max_iter)
@@ -455,33 +475,48 @@ def main():
                           f"solves/s = 1 / (ms/step x {per_col:.1f} steps per column, the mean "
                           f"iteration count of the GPU batched solve)")}
 
-    # roofline of the dominant kernel (the grouped MFMA kernel of the forward apply):
-    # algorithmic flops 8 R E_Z and bytes 8 E_Z (factors) + 8 R sum(m + n) (vectors)
-    launches = st["fwd_stages"]
-    bytes_fwd = 8.0 * st["entries_fwd"] + 8.0 * R * st["io_rows_fwd"]
-    ai = flops_fwd / bytes_fwd
-    ridge = PEAK_FP32_MFMA_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)
-    traffic = None
-    if sources_sha256() == MEASURED_TRAFFIC["sources_sha256"]:
-        traffic = MEASURED_TRAFFIC["bytes_per_apply"] / MEASURED_TRAFFIC["launches_per_apply"]
-    if ai < ridge:
-        ach = bytes_fwd / t_fwd / 1e9
-        roof = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": ach / PEAK_HBM_GBS}
-    else:
-        ach = flops_fwd / t_fwd / 1e12
-        roof = {"bound": "mfma", "achieved": ach, "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
-                "frac": ach / PEAK_FP32_MFMA_TFLOPS}
-    roof["per_stage"] = stage_roofline(op, st, R, t_fwd)
+    # roofline of a grouped kernel over one apply at R columns: algorithmic flops 8 R E and
+    # bytes 8 E (factors) + 8 R io_rows (per launch: output rows once, distinct input rows
+    # once); the bound is the side of the ridge the arithmetic intensity falls on
+    same_src = sources_sha256() == MEASURED_TRAFFIC["sources_sha256"]
+
+    def roofline(entries, io_rows, launches, t, peak_tflops, kernel, key):
+        fl = 8.0 * R * entries
+        by = 8.0 * entries + 8.0 * R * io_rows
+        ai = fl / by
+        ridge = peak_tflops * 1e12 / (PEAK_HBM_GBS * 1e9)
+        mt = MEASURED_TRAFFIC[key]
+        traffic = (mt["bytes_per_apply"] / mt["launches_per_apply"]
+                   if same_src and mt["bytes_per_apply"] else None)
+        if ai < ridge:
+            ach = by / t / 1e9
+            r = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                 "frac": ach / PEAK_HBM_GBS}
+        else:
+            ach = fl / t / 1e12
+            r = {"bound": "mfma", "achieved": ach, "peak": peak_tflops, "unit": "TFLOP/s",
+                 "frac": ach / peak_tflops}
+        r.update({"traffic": traffic, "traffic_unit": "bytes per launch",
+                  "algorithmic_bytes_per_launch": by / launches,
+                  "algorithmic_flops_per_launch": fl / launches,
+                  "arithmetic_intensity": ai, "ridge": ridge, "tflops": fl / t / 1e12,
+                  "gbs": by / t / 1e9, "kernel": kernel, "launches_per_apply": launches,
+                  "avg_launch_us": t / launches * 1e6})
+        return r
+
+    # the dominant kernel of the timed solves is the preconditioner's (about two thirds
+    # of a step); the forward kernel's roofline is reported beside it
+    roof = roofline(st["entries_pre"], st["io_rows_pre"], st["pre_stages"], t_pre[MIXED],
+                    PEAK_BF16_MFMA_TFLOPS,
+                    "k_grouped_mfma_s3 (preconditioner apply, FP32 factors on split-BF16 MFMA, "
+                    "all launches)", "precond_s3")
     copy_gbs = measured_copy_gbs()
     roof["measured_peaks"] = {"hbm_copy_gbs": copy_gbs}
-    roof.update({"traffic": traffic, "traffic_unit": "bytes per launch",
-                 "algorithmic_bytes_per_launch": bytes_fwd / launches,
-                 "algorithmic_flops_per_launch": flops_fwd / launches,
-                 "arithmetic_intensity": ai, "ridge": ridge,
-                 "tflops": flops_fwd / t_fwd / 1e12, "mfma_frac": flops_fwd / t_fwd / 1e12 / PEAK_FP32_MFMA_TFLOPS,
-                 "kernel": "k_grouped_mfma_f32 (forward apply, all launches)",
-                 "launches_per_apply": launches, "avg_launch_us": t_fwd / launches * 1e6})
+    roof_fwd = roofline(st["entries_fwd"], st["io_rows_fwd"], st["fwd_stages"], t_fwd,
+                        PEAK_FP32_MFMA_TFLOPS, "k_grouped_mfma_f32 (forward apply, all launches)",
+                        "forward_f32")
+    roof_fwd["per_stage"] = stage_roofline(op, st, R, t_fwd)
+    roof_fwd["mfma_frac"] = flops_fwd / t_fwd / 1e12 / PEAK_FP32_MFMA_TFLOPS
     out = {
         "metric": "HOD-BF apply GFLOP/s + solves/sec at 1e-4 rel. residual, mixed vs plain FP32",
         "value": solves_per_s,
@@ -493,18 +528,20 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 apply / f32 precond / f64 krylov",
+        "dtype": "c64 forward on f32 mfma / c64 precond on split-bf16 mfma, f32 accumulate / c128 krylov",
         "data": "synthetic",
         "config": {"workload": "32^3 voxels, 4-wavelength cube, eps_r iid U[2,10], 64 plane waves",
                    "n": g.n, "nrhs": R, "leaf": 64, "tol_con": cfg["tol"],
                    "tol_fact": args.tol_fact, "tol_sol": TOL_SOL, "parallelism": "1 GPU"},
         "apply_gflops": flops_fwd / t_fwd / 1e9,
         "apply_ms": t_fwd * 1e3,
+        "precond_apply_ms": t_pre[MIXED] * 1e3,
         "precond_apply_ms_fp32": t_pre["fp32"] * 1e3,
+        "precond_arithmetic": MIXED,
         "batched_solves_per_s": solves_per_s,
         "plain_fp32_solves_per_s": plain_solves_per_s,
         "batched_vs_plain": solves_per_s / plain_solves_per_s,
-        "reduced_precision_precond": variants,
+        "other_precond_arithmetic": variants,
         "iters_batched_max": max(iters),
         "iters_batched_mean": iters_mean,
         "iters_plain": plain_iters,
@@ -515,6 +552,7 @@ def main():
         "entries_pre": st["entries_pre"],
         "max_rank": st["max_rank"],
         "roofline": roof,
+        "roofline_forward": roof_fwd,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -81,13 +81,16 @@ class Server:
     def __init__(self, hbm_budget: int, slots: int = 4, max_rhs: int = 64, tol_con: float = 1e-4,
                  tol_fact: float = 1e-4, precond: int = P_FP32, restart: int = 20,
                  max_iter: int = 3000, est_bytes_per_unknown: float = 90_000.0,
-                 operator_factory=None, build_slots: int = 1):
+                 operator_factory=None, build_slots: int = 1, use_precond="fp32_split"):
         self.budget = int(hbm_budget)
         self.slots = slots
         self.max_rhs = max_rhs
         self.build_kw = dict(tol_con=tol_con, tol_fact=tol_fact, precond=precond)
         self.restart = restart
         self.max_iter = max_iter
+        # preconditioner arithmetic of every solve (Operator.solve's use_precond); the
+        # default is the mixed form: the FP32 copy on split-BF16 MFMA
+        self.use_precond = use_precond
         self.est_per_unknown = est_bytes_per_unknown  # until a real build reports its size
         self._lock = threading.Condition()
         self._pending: list = []              # (request, future, submitted)
@@ -264,7 +267,7 @@ class Server:
                 b = op.plane_wave(dirs)
                 tol = min(item[0].tol for item in batch)
                 x, info = op.solve(b, tol=tol, restart=self.restart, max_iter=self.max_iter,
-                                   use_precond=1)
+                                   use_precond=self.use_precond)
                 xh = x.cpu().numpy()
             if stream is not None:
                 stream.synchronize()
