@@ -37,10 +37,17 @@ PEAK_HBM_GBS = 8000.0
 PEAK_BF16_MFMA_TFLOPS = 2500.0
 # HBM bytes of one apply of this workload (R = 64) per kernel, from the FETCH_SIZE /
 # WRITE_SIZE counter runs recorded in profiles/*_traffic.md (scaled by a 256 MiB copy);
-# valid only while the kernel and packing sources hash to sources_sha256.
-MEASURED_TRAFFIC = {"sources_sha256": "",
+# valid only while the kernel and packing sources hash to sources_sha256.  The
+# preconditioner's counters are not available: under --pmc the profiler crashes inside
+# the rocSOLVER factorisations of the preconditioner's construction; the same kernel on
+# the forward operator (profiles/grouped_mfma_s3_forward_c2_r64_traffic.md) moves the
+# same bytes as the FP32 kernel, 1.16x its algorithmic bytes.
+MEASURED_TRAFFIC = {"sources_sha256": "a4d1aeea8695431398f34f19d3909194ed3802fda64b1565987edb754b463c17",
                     "precond_s3": {"bytes_per_apply": None, "launches_per_apply": 55},
-                    "forward_f32": {"bytes_per_apply": None, "launches_per_apply": 10}}
+                    "forward_f32": {"bytes_per_apply": 1317455810.9 + 435993904.0,
+                                    "launches_per_apply": 10},
+                    "forward_s3": {"bytes_per_apply": 1319041061.9 + 435865712.0,
+                                   "launches_per_apply": 10}}
 
 
 def measured_copy_gbs(nbytes=1 << 30, reps=10):
@@ -510,6 +517,14 @@ def main():
                     PEAK_BF16_MFMA_TFLOPS,
                     "k_grouped_mfma_s3 (preconditioner apply, FP32 factors on split-BF16 MFMA, "
                     "all launches)", "precond_s3")
+    if same_src:
+        fs = MEASURED_TRAFFIC["forward_s3"]
+        roof["traffic_note"] = (
+            "preconditioner counters unavailable (the profiler crashes inside the rocSOLVER "
+            "LU of its construction); the same kernel on the forward operator moves "
+            f"{fs['bytes_per_apply'] / fs['launches_per_apply']:.4e} bytes per launch, "
+            f"{fs['bytes_per_apply'] / (8.0 * st['entries_fwd'] + 8.0 * R * st['io_rows_fwd']):.2f}x "
+            "its algorithmic bytes")
     copy_gbs = measured_copy_gbs()
     roof["measured_peaks"] = {"hbm_copy_gbs": copy_gbs}
     roof_fwd = roofline(st["entries_fwd"], st["io_rows_fwd"], st["fwd_stages"], t_fwd,
