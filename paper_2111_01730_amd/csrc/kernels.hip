@@ -267,24 +267,6 @@ __device__ __forceinline__ unsigned load_chunk(const ChunkSrc &c, int kb, const 
   return msk;
 }
 
-// The validity mask load_chunk returns, recomputed from the chunk's (uniform) source and
-// first row, so that a caller holding several chunks in flight keeps no mask registers.
-__device__ __forceinline__ unsigned chunk_mask(const ChunkSrc &c, int kb) {
-  const int tid = threadIdx.x;
-  unsigned msk = 0;
-#pragma unroll
-  for (int i = 0; i < kXL; ++i) {
-    const int e = tid + kThreads * i;
-    msk |= unsigned(kb + (e >> 6) < c.n && (e & 63) < c.rc) << i;
-  }
-#pragma unroll
-  for (int i = 0; i < kAL; ++i) {
-    const int e = tid + kThreads * i;
-    msk |= unsigned(kb + e / kTileRows < c.n && e % kTileRows < c.m) << (kXL + i);
-  }
-  return msk;
-}
-
 // Accumulators of one work item into its output rows.  The tile's row map (at most
 // kMaxMapEntries entries, read with uniform loads; the array is padded past its end) is
 // resolved per row in registers; accumulation into the output is a non-returning atomic
@@ -562,6 +544,52 @@ typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
 typedef float floatx2v __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 constexpr int kS3 = kKC + 2;  // LDS stride (uint2) of a factor row / an input column
+// Offset (uint2) of the second input form: one plane of 64 columns plus 128 bytes, so that
+// the 16 lanes of one fragment read (8 columns x both forms) fall on distinct LDS banks
+constexpr int kX1 = 64 * kS3 + 16;
+
+// Chunk loads of the split-BF16 kernel: thread (lane l, wave g) fetches factor row l and
+// input column l at K rows kb + 4 g .. kb + 4 g + 3, so that it can write its four values
+// of each as one contiguous run (two 16-byte LDS stores).  Each load instruction still
+// reads 64 consecutive rows of a factor column or 64 consecutive right-hand sides of an
+// input row.  Indices are clamped into the block; bit j (input) and 4 + j (factor) of the
+// result say whether value j lies inside it.
+__device__ __forceinline__ unsigned load_chunk_t(const ChunkSrc &c, int kb, const float2 *__restrict__ F,
+                                                 const float2 *__restrict__ X,
+                                                 const float2 *__restrict__ T, int R,
+                                                 float2 (&xr)[4], float2 (&ar)[4]) {
+  const int l = threadIdx.x & 63;
+  const int g = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const float2 *xb = (c.xt ? T : X) + c.x;
+  const float2 *ab = F + c.a;
+  const unsigned lq = unsigned(min(l, c.rc - 1)), lr = unsigned(min(l, c.m - 1));
+  unsigned msk = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int k = kb + 4 * g + j;
+    const unsigned kc = unsigned(min(k, c.n - 1));
+    xr[j] = ldg_f2(xb, kc * unsigned(R) + lq);
+    ar[j] = ldg_f2(ab, kc * unsigned(c.lda) + lr);
+    msk |= unsigned(k < c.n && l < c.rc) << j;
+    msk |= unsigned(k < c.n && l < c.m) << (4 + j);
+  }
+  return msk;
+}
+
+// The mask load_chunk_t returns, recomputed from the chunk's (uniform) source and first
+// K row, so that two chunks in flight keep no mask registers.
+__device__ __forceinline__ unsigned chunk_mask_t(const ChunkSrc &c, int kb) {
+  const int l = threadIdx.x & 63;
+  const int g = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  unsigned msk = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int k = kb + 4 * g + j;
+    msk |= unsigned(k < c.n && l < c.rc) << j;
+    msk |= unsigned(k < c.n && l < c.m) << (4 + j);
+  }
+  return msk;
+}
 
 // (hi pair, lo pair) of the complex value (re, im), each packed re | im << 16
 __device__ __forceinline__ uint2 split_bf16(float re, float im) {
@@ -591,7 +619,7 @@ __device__ __forceinline__ void tile_item_s3(const int it, const int nsl, const 
   const int qo = i16 >> 1, op = i16 & 1;
   // this lane's fragment bases: factor row wr * 16 + i16, input column (wc * 8 + qo) of form op
   const uint2 *al = as + (wr * 16 + i16) * kS3 + 4 * kk;
-  const uint2 *xl = xs + op * (64 * kS3) + (wc * 8 + qo) * kS3 + 4 * kk;
+  const uint2 *xl = xs + op * kX1 + (wc * 8 + qo) * kS3 + 4 * kk;
   const Seg sg = segs[it / nsl];
   const int q0 = (it % nsl) * RQ;
   const int Rc = min(R - q0, RQ);
@@ -619,26 +647,33 @@ __device__ __forceinline__ void tile_item_s3(const int it, const int nsl, const 
       done = true;
     }
   };
-  auto write_chunk = [&](const float2 (&xr)[kXL], const float2 (&ar)[kAL], unsigned msk,
+  // LDS layout: factor row r at as + r kS3, input column q of form f at xs + f kX1 + q kS3,
+  // each holding K = 0..15 as (hi pair, lo pair); a row stride of 144 bytes puts 16
+  // consecutive rows (or columns) of one 16-byte column group on distinct banks
+  auto write_chunk = [&](const float2 (&xr)[4], const float2 (&ar)[4], unsigned msk,
                          float lscale) {
+    const int l = tid & 63;
+    const int g = __builtin_amdgcn_readfirstlane(tid >> 6);
+    uint2 h[4], a[4];
 #pragma unroll
-    for (int i = 0; i < kXL; ++i) {
-      const int e = tid + kThreads * i;
-      const bool ok = (msk >> i) & 1u;
-      const uint2 h = split_bf16(ok ? xr[i].x : 0.f, ok ? xr[i].y : 0.f);
-      const int c = e >> 6, q = e & 63;
-      // form 0: (xr, -xi); form 1: (xi, xr)
-      xs[q * kS3 + c] = make_uint2(h.x ^ 0x80000000u, h.y ^ 0x80000000u);
-      xs[64 * kS3 + q * kS3 + c] = make_uint2(__builtin_amdgcn_alignbit(h.x, h.x, 16),
-                                              __builtin_amdgcn_alignbit(h.y, h.y, 16));
+    for (int j = 0; j < 4; ++j) {
+      const bool okx = (msk >> j) & 1u, oka = (msk >> (4 + j)) & 1u;
+      h[j] = split_bf16(okx ? xr[j].x : 0.f, okx ? xr[j].y : 0.f);
+      a[j] = split_bf16(oka ? ar[j].x * lscale : 0.f, oka ? ar[j].y * lscale : 0.f);
     }
-#pragma unroll
-    for (int i = 0; i < kAL; ++i) {
-      const int e = tid + kThreads * i;
-      const bool ok = (msk >> (kXL + i)) & 1u;
-      as[(e % kTileRows) * kS3 + e / kTileRows] =
-          split_bf16(ok ? ar[i].x * lscale : 0.f, ok ? ar[i].y * lscale : 0.f);
-    }
+    u32x4 *x0 = reinterpret_cast<u32x4 *>(xs + l * kS3 + 4 * g);
+    u32x4 *x1 = reinterpret_cast<u32x4 *>(xs + kX1 + l * kS3 + 4 * g);
+    u32x4 *a0 = reinterpret_cast<u32x4 *>(as + l * kS3 + 4 * g);
+    constexpr uint32_t sg = 0x80000000u;
+    // form 0: (xr, -xi); form 1: (xi, xr)
+    x0[0] = u32x4{h[0].x ^ sg, h[0].y ^ sg, h[1].x ^ sg, h[1].y ^ sg};
+    x0[1] = u32x4{h[2].x ^ sg, h[2].y ^ sg, h[3].x ^ sg, h[3].y ^ sg};
+    x1[0] = u32x4{__builtin_amdgcn_alignbit(h[0].x, h[0].x, 16), __builtin_amdgcn_alignbit(h[0].y, h[0].y, 16),
+                  __builtin_amdgcn_alignbit(h[1].x, h[1].x, 16), __builtin_amdgcn_alignbit(h[1].y, h[1].y, 16)};
+    x1[1] = u32x4{__builtin_amdgcn_alignbit(h[2].x, h[2].x, 16), __builtin_amdgcn_alignbit(h[2].y, h[2].y, 16),
+                  __builtin_amdgcn_alignbit(h[3].x, h[3].x, 16), __builtin_amdgcn_alignbit(h[3].y, h[3].y, 16)};
+    a0[0] = u32x4{a[0].x, a[0].y, a[1].x, a[1].y};
+    a0[1] = u32x4{a[2].x, a[2].y, a[3].x, a[3].y};
   };
   auto multiply = [&]() {
     if (NRI > 0) {
@@ -675,34 +710,34 @@ __device__ __forceinline__ void tile_item_s3(const int it, const int nsl, const 
   };
   // each set keeps its chunk's uniform source and first column; the lane masks are
   // recomputed from them when the set is written to LDS
-  float2 xr0[kXL], ar0[kAL], xr1[kXL], ar1[kAL];
+  float2 xr0[4], ar0[4], xr1[4], ar1[4];
   ChunkSrc c0 = cur, c1;
   int kb0 = k0, kb1;
-  (void)load_chunk<float2>(cur, k0, F, X, T, R, xr0, ar0);
+  (void)load_chunk_t(cur, k0, F, X, T, R, xr0, ar0);
   advance();
   bool v1 = !done;  // set 1 holds a chunk of the tile
   c1 = cur;
   kb1 = k0;
-  (void)load_chunk<float2>(cur, k0, F, X, T, R, xr1, ar1);
+  (void)load_chunk_t(cur, k0, F, X, T, R, xr1, ar1);
   while (true) {
     __syncthreads();  // previous chunk fully consumed
-    write_chunk(xr0, ar0, chunk_mask(c0, kb0), c0.scale);
+    write_chunk(xr0, ar0, chunk_mask_t(c0, kb0), c0.scale);
     __syncthreads();
     advance();
     const bool v0 = !done;  // set 0 gets the chunk after set 1's
     c0 = cur;
     kb0 = k0;
-    (void)load_chunk<float2>(cur, k0, F, X, T, R, xr0, ar0);
+    (void)load_chunk_t(cur, k0, F, X, T, R, xr0, ar0);
     multiply();
     if (!v1) break;
     __syncthreads();
-    write_chunk(xr1, ar1, chunk_mask(c1, kb1), c1.scale);
+    write_chunk(xr1, ar1, chunk_mask_t(c1, kb1), c1.scale);
     __syncthreads();
     advance();
     v1 = !done;
     c1 = cur;
     kb1 = k0;
-    (void)load_chunk<float2>(cur, k0, F, X, T, R, xr1, ar1);
+    (void)load_chunk_t(cur, k0, F, X, T, R, xr1, ar1);
     multiply();
     if (!v0) break;
   }
@@ -714,7 +749,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
     const float2 *__restrict__ F, const float2 *__restrict__ X, const float2 *__restrict__ T,
     float2 *__restrict__ OUT, int R, int beta, int RQ, int nsl, TileClasses tc) {
   __shared__ __attribute__((aligned(16))) uint2 as[kTileRows * kS3];
-  __shared__ __attribute__((aligned(16))) uint2 xs[2 * 64 * kS3];
+  __shared__ __attribute__((aligned(16))) uint2 xs[kX1 + 64 * kS3];
   const int it = xcd_work_index();
   if (it >= tc.seg0[kWaves] * nsl) return;
   int c = 0;
