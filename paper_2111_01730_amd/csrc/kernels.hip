@@ -577,7 +577,8 @@ __device__ __forceinline__ unsigned load_chunk_t(const ChunkSrc &c, int kb, cons
 }
 
 // The mask load_chunk_t returns, recomputed from the chunk's (uniform) source and first
-// K row, so that two chunks in flight keep no mask registers.
+// K row when the chunk is written to LDS, so no mask register stays live across the
+// multiply.
 __device__ __forceinline__ unsigned chunk_mask_t(const ChunkSrc &c, int kb) {
   const int l = threadIdx.x & 63;
   const int g = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -626,10 +627,9 @@ __device__ __forceinline__ void tile_item_s3(const int it, const int nsl, const 
   floatx4 acc[NRI > 0 ? NRI * NCI : 1];
 #pragma unroll
   for (int j = 0; j < (NRI > 0 ? NRI * NCI : 1); ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
-  // The load cursor (pair p, column k0, source cur) runs two chunks ahead of the chunk
-  // being multiplied: two register sets alternate.  Past the tile's last chunk the cursor
-  // stays on it and the loads repeat it (in bounds, never used), so every iteration
-  // issues the same loads and each LDS write waits only for its own set.
+  // The load cursor (pair p, column k0, source cur) runs one chunk ahead of the chunk
+  // being multiplied: its loads are in flight during the multiply.  (Two chunks ahead in
+  // two register sets measured no faster and costs the fifth wave per SIMD.)
   ChunkSrc cur = chunk_src(sg.first, R, q0, Rc, sg.m);
   int p = sg.p0, k0 = 0;
   bool done = false;
@@ -708,43 +708,30 @@ __device__ __forceinline__ void tile_item_s3(const int it, const int nsl, const 
       }
     }
   };
-  // each set keeps its chunk's uniform source and first column; the lane masks are
-  // recomputed from them when the set is written to LDS
-  float2 xr0[4], ar0[4], xr1[4], ar1[4];
-  ChunkSrc c0 = cur, c1;
-  int kb0 = k0, kb1;
-  (void)load_chunk_t(cur, k0, F, X, T, R, xr0, ar0);
-  advance();
-  bool v1 = !done;  // set 1 holds a chunk of the tile
-  c1 = cur;
-  kb1 = k0;
-  (void)load_chunk_t(cur, k0, F, X, T, R, xr1, ar1);
+  // the registers' chunk keeps its uniform source and first column; the lane masks are
+  // recomputed from them when it is written to LDS
+  float2 xr[4], ar[4];
+  ChunkSrc cc = cur;
+  int kbc = k0;
+  (void)load_chunk_t(cur, k0, F, X, T, R, xr, ar);
   while (true) {
-    __syncthreads();  // previous chunk fully consumed
-    write_chunk(xr0, ar0, chunk_mask_t(c0, kb0), c0.scale);
+    __syncthreads();
+    write_chunk(xr, ar, chunk_mask_t(cc, kbc), cc.scale);
     __syncthreads();
     advance();
-    const bool v0 = !done;  // set 0 gets the chunk after set 1's
-    c0 = cur;
-    kb0 = k0;
-    (void)load_chunk_t(cur, k0, F, X, T, R, xr0, ar0);
+    const bool more = !done;
+    cc = cur;
+    kbc = k0;
+    if (more) (void)load_chunk_t(cur, k0, F, X, T, R, xr, ar);
     multiply();
-    if (!v1) break;
-    __syncthreads();
-    write_chunk(xr1, ar1, chunk_mask_t(c1, kb1), c1.scale);
-    __syncthreads();
-    advance();
-    v1 = !done;
-    c1 = cur;
-    kb1 = k0;
-    (void)load_chunk_t(cur, k0, F, X, T, R, xr1, ar1);
-    multiply();
-    if (!v0) break;
+    if (!more) break;
   }
   store_item<NRI, NCI, RW>(sg, rowmap, OUT, R, beta, q0, Rc, wr, wc, acc);
 }
 
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_grouped_mfma_s3(
+// Five waves per SIMD (96 VGPRs; the register allocator spills one value to scratch):
+// measured faster than four at 1-16 right-hand sides and equal at 64.
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_grouped_mfma_s3(
     const Seg *__restrict__ segs, const Pair *__restrict__ pairs, const RowMap *__restrict__ rowmap,
     const float2 *__restrict__ F, const float2 *__restrict__ X, const float2 *__restrict__ T,
     float2 *__restrict__ OUT, int R, int beta, int RQ, int nsl, TileClasses tc) {
