@@ -206,7 +206,6 @@ def apply_mode(args, cfg, Operator, P_NONE):
 
     from paper_2111_01730_amd.hodbf import P_FP32
     g = cfg["grid"]
-    R = cfg["nrhs"]
     which = args.which
     if which not in (0, 2, 5, 6):
         raise SystemExit("--which must be 0, 2, 5 or 6")
@@ -214,7 +213,9 @@ def apply_mode(args, cfg, Operator, P_NONE):
     op = Operator(g, tol_con=cfg["tol"], tol_fact=args.tol_fact if pre else 0.0,
                   precond=P_FP32 if pre else P_NONE, seed=cfg["seed"])
     st = op.stats()
-    b = op.plane_wave(cfg["dirs"])
+    dirs = np.asarray(cfg["dirs"])[: args.apply_nrhs or None]
+    R = len(dirs)
+    b = op.plane_wave(dirs)
     perm = torch.as_tensor(op.perm().astype(np.int64), device="cuda")
     xt = b[perm].to(torch.complex64).contiguous()
     ref = torch.empty(64 << 20, dtype=torch.float32, device="cuda")  # 256 MiB copy reference
@@ -236,7 +237,7 @@ def apply_mode(args, cfg, Operator, P_NONE):
     t = e0.elapsed_time(e1) / reps * 1e-3
     ent = st["entries_pre"] if pre else st["entries_fwd"]
     fl = 8.0 * R * ent
-    print(json.dumps({"mode": "apply", "which": which, "apply_ms": t * 1e3,
+    print(json.dumps({"mode": "apply", "which": which, "nrhs": R, "apply_ms": t * 1e3,
                       "apply_gflops": fl / t / 1e9,
                       "launches_per_apply": st["pre_stages"] if pre else st["fwd_stages"],
                       "entries": ent, "io_rows": st["io_rows_pre"] if pre else st["io_rows_fwd"],
@@ -355,6 +356,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-baseline-leg", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--apply-reps", type=int, default=20)
+    ap.add_argument("--apply-nrhs", type=int, default=0,
+                    help="--mode apply: right-hand sides (0: the workload's 64)")
     ap.add_argument("--which", type=int, default=0,
                     help="--mode apply: 0 forward, 6 preconditioner on split-BF16 arithmetic")
     args = ap.parse_args()
