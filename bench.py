@@ -42,11 +42,11 @@ PEAK_BF16_MFMA_TFLOPS = 2500.0
 # the rocSOLVER factorisations of the preconditioner's construction; the same kernel on
 # the forward operator (profiles/grouped_mfma_s3_forward_c2_r64_traffic.md) moves the
 # same bytes as the FP32 kernel, 1.16x its algorithmic bytes.
-MEASURED_TRAFFIC = {"sources_sha256": "a4d1aeea8695431398f34f19d3909194ed3802fda64b1565987edb754b463c17",
+MEASURED_TRAFFIC = {"sources_sha256": "6d20ae3c9cad9d0424c68e10a9048005fd60d6769cf33d26c2253206724a557a",
                     "precond_s3": {"bytes_per_apply": None, "launches_per_apply": 55},
-                    "forward_f32": {"bytes_per_apply": 1317455810.9 + 435993904.0,
+                    "forward_f32": {"bytes_per_apply": 1317314009.0 + 435994528.0,
                                     "launches_per_apply": 10},
-                    "forward_s3": {"bytes_per_apply": 1319041061.9 + 435865712.0,
+                    "forward_s3": {"bytes_per_apply": 1322204102.1 + 442023184.0,
                                    "launches_per_apply": 10}}
 
 
