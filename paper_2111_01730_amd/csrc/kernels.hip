@@ -81,6 +81,13 @@ __device__ inline float2 ldg_f2(const float2 *p, int64_t idx) {
   const gfloat2v v = ((const __attribute__((address_space(1))) gfloat2v *)p)[idx];
   return make_float2(v.x, v.y);
 }
+// A uniform base plus a 32-bit byte offset per lane: the global_load's scalar-base form,
+// with no 64-bit address arithmetic per lane.
+__device__ inline float2 ldg_f2_sb(const float2 *base, uint32_t byte_off) {
+  typedef const __attribute__((address_space(1))) char gchar;
+  const gfloat2v v = *(const __attribute__((address_space(1))) gfloat2v *)((gchar *)base + byte_off);
+  return make_float2(v.x, v.y);
+}
 __device__ inline uint32_t ldg_u32(const uint32_t *p, int64_t idx) {
   return ((const __attribute__((address_space(1))) uint32_t *)p)[idx];
 }
@@ -543,18 +550,23 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
 typedef float floatx2v __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-constexpr int kS3 = kKC + 2;  // LDS stride (uint2) of a factor row / an input column
-// Offset (uint2) of the second input form: one plane of 64 columns plus 128 bytes, so that
-// the 16 lanes of one fragment read (8 columns x both forms) fall on distinct LDS banks
-constexpr int kX1 = 64 * kS3 + 16;
+// LDS planes of the split-BF16 kernel (32-bit words): hi and lo parts apart, so that a
+// fragment is one 16-byte read straight into the MFMA operand registers.  A plane holds
+// 64 rows (factor) or 64 right-hand-side columns (input) of kS3 words, K = 0..15 packed
+// (re | im << 16) in words 0..15 of each.  A stride of 20 words puts 16 consecutive rows
+// of one 4-word K group on distinct banks; the second input form sits 32 words further
+// modulo 64, so the 16 lanes of an input fragment read (8 columns x both forms) do too.
+constexpr int kS3 = kKC + 4;
+constexpr int kPlane = 64 * kS3;     // words of one plane
+constexpr int kXF = 2 * kPlane + 32;  // words between the two input forms (hi + lo planes each)
 
 // Chunk loads of the split-BF16 kernel: thread (lane l, wave g) fetches factor row l and
 // input column l at K rows kb + 4 g .. kb + 4 g + 3, so that it can write its four values
 // of each as one contiguous run (two 16-byte LDS stores).  Each load instruction still
 // reads 64 consecutive rows of a factor column or 64 consecutive right-hand sides of an
-// input row.  Indices are clamped into the block; bit j (input) and 4 + j (factor) of the
-// result say whether value j lies inside it.
-__device__ __forceinline__ unsigned load_chunk_t(const ChunkSrc &c, int kb, const float2 *__restrict__ F,
+// input row.  Indices are clamped into the block (the write to LDS zeroes what lies
+// outside it).
+__device__ __forceinline__ void load_chunk_t(const ChunkSrc &c, int kb, const float2 *__restrict__ F,
                                                  const float2 *__restrict__ X,
                                                  const float2 *__restrict__ T, int R,
                                                  float2 (&xr)[4], float2 (&ar)[4]) {
@@ -563,33 +575,12 @@ __device__ __forceinline__ unsigned load_chunk_t(const ChunkSrc &c, int kb, cons
   const float2 *xb = (c.xt ? T : X) + c.x;
   const float2 *ab = F + c.a;
   const unsigned lq = unsigned(min(l, c.rc - 1)), lr = unsigned(min(l, c.m - 1));
-  unsigned msk = 0;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    const int k = kb + 4 * g + j;
-    const unsigned kc = unsigned(min(k, c.n - 1));
-    xr[j] = ldg_f2(xb, kc * unsigned(R) + lq);
-    ar[j] = ldg_f2(ab, kc * unsigned(c.lda) + lr);
-    msk |= unsigned(k < c.n && l < c.rc) << j;
-    msk |= unsigned(k < c.n && l < c.m) << (4 + j);
+    const unsigned kc = unsigned(min(kb + 4 * g + j, c.n - 1));
+    xr[j] = ldg_f2_sb(xb, (kc * unsigned(R) + lq) * 8u);
+    ar[j] = ldg_f2_sb(ab, (kc * unsigned(c.lda) + lr) * 8u);
   }
-  return msk;
-}
-
-// The mask load_chunk_t returns, recomputed from the chunk's (uniform) source and first
-// K row when the chunk is written to LDS, so no mask register stays live across the
-// multiply.
-__device__ __forceinline__ unsigned chunk_mask_t(const ChunkSrc &c, int kb) {
-  const int l = threadIdx.x & 63;
-  const int g = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  unsigned msk = 0;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int k = kb + 4 * g + j;
-    msk |= unsigned(k < c.n && l < c.rc) << j;
-    msk |= unsigned(k < c.n && l < c.m) << (4 + j);
-  }
-  return msk;
 }
 
 // (hi pair, lo pair) of the complex value (re, im), each packed re | im << 16
@@ -612,15 +603,16 @@ __device__ __forceinline__ void tile_item_s3(const int it, const int nsl, const 
                                              const float2 *__restrict__ T,
                                              float2 *__restrict__ OUT, const int R,
                                              const int beta, const int wr, const int wc,
-                                             uint2 *as, uint2 *xs) {
+                                             uint32_t *as, uint32_t *xs) {
   constexpr int CW = kWaves / RW;
   const int tid = threadIdx.x, lane = tid & 63;
   const int i16 = lane & 15;
   const int kk = lane >> 4;
   const int qo = i16 >> 1, op = i16 & 1;
-  // this lane's fragment bases: factor row wr * 16 + i16, input column (wc * 8 + qo) of form op
-  const uint2 *al = as + (wr * 16 + i16) * kS3 + 4 * kk;
-  const uint2 *xl = xs + op * kX1 + (wc * 8 + qo) * kS3 + 4 * kk;
+  // this lane's fragment bases (hi planes; lo at + kPlane): factor row wr * 16 + i16, input
+  // column wc * 8 + qo of form op, K group kk
+  const uint32_t *al = as + (wr * 16 + i16) * kS3 + 4 * kk;
+  const uint32_t *xl = xs + op * kXF + (wc * 8 + qo) * kS3 + 4 * kk;
   const Seg sg = segs[it / nsl];
   const int q0 = (it % nsl) * RQ;
   const int Rc = min(R - q0, RQ);
@@ -647,52 +639,52 @@ __device__ __forceinline__ void tile_item_s3(const int it, const int nsl, const 
       done = true;
     }
   };
-  // LDS layout: factor row r at as + r kS3, input column q of form f at xs + f kX1 + q kS3,
-  // each holding K = 0..15 as (hi pair, lo pair); a row stride of 144 bytes puts 16
-  // consecutive rows (or columns) of one 16-byte column group on distinct banks
-  auto write_chunk = [&](const float2 (&xr)[4], const float2 (&ar)[4], unsigned msk,
-                         float lscale) {
+  // thread (l, g) writes K = 4 g .. 4 g + 3 of factor row l and of input column l: one
+  // 16-byte store per plane
+  // values outside the block (K row kb + 4 g + j past the pair's columns: a wave-uniform
+  // test; lane l past the slice's columns or the tile's rows) are written as zeros
+  auto write_chunk = [&](const float2 (&xr)[4], const float2 (&ar)[4], const ChunkSrc &c,
+                         int kb) {
     const int l = tid & 63;
     const int g = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const bool lx = l < c.rc, la = l < c.m;
     uint2 h[4], a[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const bool okx = (msk >> j) & 1u, oka = (msk >> (4 + j)) & 1u;
+      const bool kv = kb + 4 * g + j < c.n;
+      const bool okx = kv && lx, oka = kv && la;
       h[j] = split_bf16(okx ? xr[j].x : 0.f, okx ? xr[j].y : 0.f);
-      a[j] = split_bf16(oka ? ar[j].x * lscale : 0.f, oka ? ar[j].y * lscale : 0.f);
+      a[j] = split_bf16(oka ? ar[j].x * c.scale : 0.f, oka ? ar[j].y * c.scale : 0.f);
     }
-    u32x4 *x0 = reinterpret_cast<u32x4 *>(xs + l * kS3 + 4 * g);
-    u32x4 *x1 = reinterpret_cast<u32x4 *>(xs + kX1 + l * kS3 + 4 * g);
-    u32x4 *a0 = reinterpret_cast<u32x4 *>(as + l * kS3 + 4 * g);
+    const int o = l * kS3 + 4 * g;
     constexpr uint32_t sg = 0x80000000u;
+    auto rot = [](uint32_t v) { return __builtin_amdgcn_alignbit(v, v, 16); };
+    *reinterpret_cast<u32x4 *>(as + o) = u32x4{a[0].x, a[1].x, a[2].x, a[3].x};
+    *reinterpret_cast<u32x4 *>(as + kPlane + o) = u32x4{a[0].y, a[1].y, a[2].y, a[3].y};
     // form 0: (xr, -xi); form 1: (xi, xr)
-    x0[0] = u32x4{h[0].x ^ sg, h[0].y ^ sg, h[1].x ^ sg, h[1].y ^ sg};
-    x0[1] = u32x4{h[2].x ^ sg, h[2].y ^ sg, h[3].x ^ sg, h[3].y ^ sg};
-    x1[0] = u32x4{__builtin_amdgcn_alignbit(h[0].x, h[0].x, 16), __builtin_amdgcn_alignbit(h[0].y, h[0].y, 16),
-                  __builtin_amdgcn_alignbit(h[1].x, h[1].x, 16), __builtin_amdgcn_alignbit(h[1].y, h[1].y, 16)};
-    x1[1] = u32x4{__builtin_amdgcn_alignbit(h[2].x, h[2].x, 16), __builtin_amdgcn_alignbit(h[2].y, h[2].y, 16),
-                  __builtin_amdgcn_alignbit(h[3].x, h[3].x, 16), __builtin_amdgcn_alignbit(h[3].y, h[3].y, 16)};
-    a0[0] = u32x4{a[0].x, a[0].y, a[1].x, a[1].y};
-    a0[1] = u32x4{a[2].x, a[2].y, a[3].x, a[3].y};
+    *reinterpret_cast<u32x4 *>(xs + o) = u32x4{h[0].x ^ sg, h[1].x ^ sg, h[2].x ^ sg, h[3].x ^ sg};
+    *reinterpret_cast<u32x4 *>(xs + kPlane + o) =
+        u32x4{h[0].y ^ sg, h[1].y ^ sg, h[2].y ^ sg, h[3].y ^ sg};
+    *reinterpret_cast<u32x4 *>(xs + kXF + o) = u32x4{rot(h[0].x), rot(h[1].x), rot(h[2].x), rot(h[3].x)};
+    *reinterpret_cast<u32x4 *>(xs + kXF + kPlane + o) =
+        u32x4{rot(h[0].y), rot(h[1].y), rot(h[2].y), rot(h[3].y)};
   };
   auto multiply = [&]() {
     if (NRI > 0) {
       bf16x8 xh[NCI], xo[NCI];
 #pragma unroll
       for (int ci = 0; ci < NCI; ++ci) {
-        const u32x4 *b = reinterpret_cast<const u32x4 *>(xl + ci * CW * 8 * kS3);
-        const u32x4 b0 = b[0], b1 = b[1];  // (hi, lo) of complex columns 4 kk .. 4 kk + 3
-        xh[ci] = __builtin_bit_cast(bf16x8, u32x4{b0.x, b0.z, b1.x, b1.z});
-        xo[ci] = __builtin_bit_cast(bf16x8, u32x4{b0.y, b0.w, b1.y, b1.w});
+        const uint32_t *b = xl + ci * CW * 8 * kS3;
+        xh[ci] = *reinterpret_cast<const bf16x8 *>(b);
+        xo[ci] = *reinterpret_cast<const bf16x8 *>(b + kPlane);
       }
       // one row tile at a time (its fragments are used by NCI column tiles); within it the
       // three products run term-major, so consecutive MFMAs alternate accumulators
 #pragma unroll
       for (int ri = 0; ri < NRI; ++ri) {
-        const u32x4 *a = reinterpret_cast<const u32x4 *>(al + ri * RW * 16 * kS3);
-        const u32x4 a0 = a[0], a1 = a[1];
-        const bf16x8 ah = __builtin_bit_cast(bf16x8, u32x4{a0.x, a0.z, a1.x, a1.z});
-        const bf16x8 ao = __builtin_bit_cast(bf16x8, u32x4{a0.y, a0.w, a1.y, a1.w});
+        const uint32_t *a = al + ri * RW * 16 * kS3;
+        const bf16x8 ah = *reinterpret_cast<const bf16x8 *>(a);
+        const bf16x8 ao = *reinterpret_cast<const bf16x8 *>(a + kPlane);
 #pragma unroll
         for (int ci = 0; ci < NCI; ++ci)
           acc[ri * NCI + ci] =
@@ -713,16 +705,16 @@ __device__ __forceinline__ void tile_item_s3(const int it, const int nsl, const 
   float2 xr[4], ar[4];
   ChunkSrc cc = cur;
   int kbc = k0;
-  (void)load_chunk_t(cur, k0, F, X, T, R, xr, ar);
+  load_chunk_t(cur, k0, F, X, T, R, xr, ar);
   while (true) {
     __syncthreads();
-    write_chunk(xr, ar, chunk_mask_t(cc, kbc), cc.scale);
+    write_chunk(xr, ar, cc, kbc);
     __syncthreads();
     advance();
     const bool more = !done;
     cc = cur;
     kbc = k0;
-    if (more) (void)load_chunk_t(cur, k0, F, X, T, R, xr, ar);
+    if (more) load_chunk_t(cur, k0, F, X, T, R, xr, ar);
     multiply();
     if (!more) break;
   }
@@ -735,8 +727,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5, 8))
     const Seg *__restrict__ segs, const Pair *__restrict__ pairs, const RowMap *__restrict__ rowmap,
     const float2 *__restrict__ F, const float2 *__restrict__ X, const float2 *__restrict__ T,
     float2 *__restrict__ OUT, int R, int beta, int RQ, int nsl, TileClasses tc) {
-  __shared__ __attribute__((aligned(16))) uint2 as[kTileRows * kS3];
-  __shared__ __attribute__((aligned(16))) uint2 xs[kX1 + 64 * kS3];
+  static_assert(kTileRows == 64, "one plane row per tile row");
+  __shared__ __attribute__((aligned(16))) uint32_t as[2 * kPlane];
+  __shared__ __attribute__((aligned(16))) uint32_t xs[kXF + 2 * kPlane];
   const int it = xcd_work_index();
   if (it >= tc.seg0[kWaves] * nsl) return;
   int c = 0;
