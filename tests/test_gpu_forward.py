@@ -160,6 +160,17 @@ def test_zero_rhs_and_errors(hod):
     assert op.apply(x).shape == (g.n, 0)
     with pytest.raises(HodbfError):
         op.precond_apply(torch.zeros(g.n, dtype=torch.complex64, device="cuda"))
+    xt = torch.zeros((g.n, 2), dtype=torch.complex64, device="cuda")
+    for bad_which in (-1, 7):
+        with pytest.raises(HodbfError):
+            op.apply_tree(xt, bad_which)
+    with pytest.raises(HodbfError):  # split arithmetic of a preconditioner that was not built
+        op.apply_tree(xt, 6)
+    b = torch.ones((g.n, 1), dtype=torch.complex128, device="cuda")
+    with pytest.raises(HodbfError):
+        op.solve(b, use_precond="fp32_split")
+    with pytest.raises(HodbfError):  # no split form of the BF16 copy
+        op.solve(b, use_precond=16 + hod.P_BF16)
 
 
 def test_gmres_unpreconditioned_matches_lu(hod):
