@@ -42,11 +42,11 @@ PEAK_BF16_MFMA_TFLOPS = 2500.0
 # the rocSOLVER factorisations of the preconditioner's construction; the same kernel on
 # the forward operator (profiles/grouped_mfma_s3_forward_c2_r64_traffic.md) moves the
 # same bytes as the FP32 kernel, 1.16x its algorithmic bytes.
-MEASURED_TRAFFIC = {"sources_sha256": "6d20ae3c9cad9d0424c68e10a9048005fd60d6769cf33d26c2253206724a557a",
+MEASURED_TRAFFIC = {"sources_sha256": "e3c2d291fe8558b4352a3843d03eddda66df997593cf578ca9a526adb87f3b7c",
                     "precond_s3": {"bytes_per_apply": None, "launches_per_apply": 55},
-                    "forward_f32": {"bytes_per_apply": 1317314009.0 + 435994528.0,
+                    "forward_f32": {"bytes_per_apply": 1317482834.7 + 435991248.0,
                                     "launches_per_apply": 10},
-                    "forward_s3": {"bytes_per_apply": 1322204102.1 + 442023184.0,
+                    "forward_s3": {"bytes_per_apply": 1315883952.3 + 435857680.0,
                                    "launches_per_apply": 10}}
 
 
@@ -305,7 +305,7 @@ def config_mode(args):
     perm = torch.as_tensor(op.perm().astype(np.int64), device="cuda")
     xt = b[perm].to(torch.complex64).contiguous()
     times = {}
-    for name, which in (("forward", 0), ("precond_fp32", 2)):
+    for name, which in (("forward", 0), ("precond_fp32", 2), ("precond_fp32_split", 6)):
         for _ in range(2):
             op.apply_tree(xt, which)
         torch.cuda.synchronize()
@@ -314,10 +314,22 @@ def config_mode(args):
             op.apply_tree(xt, which)
         torch.cuda.synchronize()
         times[name] = (time.perf_counter() - ta) / 5
-    tsol = time.perf_counter()
-    x, info = op.solve(b, tol=tol, restart=args.restart, max_iter=args.max_iter, use_precond="fp32")
-    torch.cuda.synchronize()
-    solve_s = time.perf_counter() - tsol
+    # the all-FP32 solve and the mixed one (FP32 forward, split-BF16 preconditioner)
+    solves = {}
+    for arith in ("fp32", "fp32_split"):
+        torch.cuda.synchronize()
+        tsol = time.perf_counter()
+        x, info = op.solve(b, tol=tol, restart=args.restart, max_iter=args.max_iter,
+                           use_precond=arith)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - tsol
+        solves[arith] = {"solve_s": dt, "solves_per_s": R / dt,
+                         "iters_max": int(info["iters"].max()),
+                         "iters_mean": float(info["iters"].mean()),
+                         "converged": bool(info["converged"].all()),
+                         "relres_max": float(info["relres"].max())}
+        log(f"[solve {arith}] {solves[arith]}")
+    solve_s = solves["fp32"]["solve_s"]
     out = {"mode": "config", "config": args.config, "n": g.n, "nrhs": R, "tol_con": tol,
            "tol_fact": args.tol_fact, "precond_min_level": args.precond_min_level,
            "build_s": build_s, "forward_build_s": st["build_seconds"],
@@ -327,10 +339,8 @@ def config_mode(args):
            "forward_apply_ms": times["forward"] * 1e3,
            "forward_gflops": 8.0 * R * st["entries_fwd"] / times["forward"] / 1e9,
            "precond_apply_ms": times["precond_fp32"] * 1e3,
-           "solve_s": solve_s, "solves_per_s": R / solve_s,
-           "iters_max": int(info["iters"].max()), "iters_mean": float(info["iters"].mean()),
-           "converged": bool(info["converged"].all()), "relres_max": float(info["relres"].max()),
-           "restart": args.restart}
+           "precond_apply_ms_split": times["precond_fp32_split"] * 1e3,
+           "solve_s": solve_s, "solves": solves, "restart": args.restart}
     print(json.dumps(out), flush=True)
     return 0
 
