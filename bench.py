@@ -211,7 +211,8 @@ def apply_mode(args, cfg, Operator, P_NONE):
         raise SystemExit("--which must be 0, 2, 5 or 6")
     pre = which in (2, 6)
     op = Operator(g, tol_con=cfg["tol"], tol_fact=args.tol_fact if pre else 0.0,
-                  precond=P_FP32 if pre else P_NONE, seed=cfg["seed"])
+                  precond=P_FP32 if pre else P_NONE, seed=cfg["seed"],
+                  precond_dense_levels=args.precond_dense_levels if pre else 0)
     st = op.stats()
     dirs = np.asarray(cfg["dirs"])[: args.apply_nrhs or None]
     R = len(dirs)
@@ -355,6 +356,9 @@ def main():
                     default="solve")
     ap.add_argument("--config", default="c3_sphere_64", help="workload of --mode config")
     ap.add_argument("--precond-min-level", type=int, default=0)
+    ap.add_argument("--precond-dense-levels", type=int, default=4,
+                    help="solve / apply modes: tree levels (above the leaves) whose "
+                         "preconditioner factors are replaced by dense node inverses")
     ap.add_argument("--restart", type=int, default=20)
     ap.add_argument("--max-iter", type=int, default=3000)
     ap.add_argument("--serve-requests", type=int, default=200)
@@ -402,7 +406,8 @@ def main():
         return config_mode(args)
     t0 = time.perf_counter()
     op = Operator(g, tol_con=cfg["tol"], tol_fact=args.tol_fact, precond=P_FP32 | P_BF16 | P_FP16,
-                  seed=cfg["seed"])
+                  seed=cfg["seed"],
+                  precond_dense_levels=args.precond_dense_levels)
     build_s = time.perf_counter() - t0
     st = op.stats()
     log(f"[build] {build_s:.1f}s stats={st}")
@@ -560,7 +565,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "32^3 voxels, 4-wavelength cube, eps_r iid U[2,10], 64 plane waves",
                    "n": g.n, "nrhs": R, "leaf": 64, "tol_con": cfg["tol"],
-                   "tol_fact": args.tol_fact, "tol_sol": TOL_SOL, "parallelism": "1 GPU"},
+                   "tol_fact": args.tol_fact, "tol_sol": TOL_SOL,
+                   "precond_dense_levels": args.precond_dense_levels, "parallelism": "1 GPU"},
         "apply_gflops": flops_fwd / t_fwd / 1e9,
         "apply_ms": t_fwd * 1e3,
         "precond_apply_ms": t_pre[MIXED] * 1e3,

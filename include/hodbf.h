@@ -83,6 +83,12 @@ typedef struct {
   int32_t leaf_size;     /* leaf cluster size of T_H, 1..64 (64 recommended) */
   int32_t precond_prec;  /* hodbf_prec bit mask, 0..7 */
   int32_t precond_min_level; /* levels < this get no X_tau (0 = full Algorithm 1 form) */
+  int32_t precond_dense_levels; /* d >= 0: the leaf inverses and the X_tau of the d lowest
+                                   tree levels are replaced by the exact dense inverses of
+                                   the diagonal blocks Z(tau, tau) of the level L_H - d
+                                   nodes (what those factors compose to, Algorithm 1, up to
+                                   chi_fact); 0 = leaves of the tree; E_ARG if L_H - d <
+                                   precond_min_level (clamped to L_H otherwise) */
   uint64_t seed;         /* row-sampling RNG seed */
   size_t hbm_budget;     /* bytes of device memory the operator may hold; 0 = unlimited */
   void *stream;          /* hipStream_t used for construction */

@@ -30,7 +30,7 @@ class BuildParams(C.Structure):
                 ("h", C.c_double), ("k0", C.c_double), ("eps_r", C.POINTER(C.c_double)),
                 ("tol_con", C.c_double), ("tol_fact", C.c_double), ("leaf_size", C.c_int32),
                 ("precond_prec", C.c_int32), ("precond_min_level", C.c_int32),
-                ("seed", C.c_uint64), ("hbm_budget", C.c_size_t), ("stream", C.c_void_p)]
+                ("precond_dense_levels", C.c_int32), ("seed", C.c_uint64), ("hbm_budget", C.c_size_t), ("stream", C.c_void_p)]
 
 
 class SolveOpts(C.Structure):
@@ -102,12 +102,13 @@ def check(code: int):
 
 
 def make_params(grid, tol_con, tol_fact=0.0, leaf_size=64, precond_prec=P_NONE,
-                precond_min_level=0, seed=1, hbm_budget=0, stream=None):
+                precond_min_level=0, seed=1, hbm_budget=0, stream=None, precond_dense_levels=0):
     eps = np.ascontiguousarray(np.asarray(grid.eps, dtype=np.complex128)).view(np.float64)
     p = BuildParams(nx=grid.nx, ny=grid.ny, nz=grid.nz, h=grid.h, k0=grid.k0,
                     eps_r=eps.ctypes.data_as(C.POINTER(C.c_double)), tol_con=tol_con,
                     tol_fact=tol_fact, leaf_size=leaf_size, precond_prec=precond_prec,
-                    precond_min_level=precond_min_level, seed=seed, hbm_budget=hbm_budget,
+                    precond_min_level=precond_min_level,
+                    precond_dense_levels=precond_dense_levels, seed=seed, hbm_budget=hbm_budget,
                     stream=stream)
     p._keep = eps  # keep the host array alive with the struct
     return p

@@ -212,6 +212,7 @@ void validate_params(const hodbf_build_params &p) {
   if (p.precond_prec < 0 || p.precond_prec > 7)
     fail(HODBF_E_ARG, "unknown precond_prec");
   if (p.precond_min_level < 0) fail(HODBF_E_ARG, "precond_min_level must be >= 0");
+  if (p.precond_dense_levels < 0) fail(HODBF_E_ARG, "precond_dense_levels must be >= 0");
   if (!p.eps_r) fail(HODBF_E_ARG, "eps_r is NULL");
   const int64_t n = int64_t(p.nx) * p.ny * p.nz;
   for (int64_t i = 0; i < 2 * n; ++i)

@@ -171,6 +171,53 @@ static void dense_x(hodbf_op &op, rocblas_handle rh, int l, int64_t tau, std::ve
       fail(HODBF_E_NUMERIC, "non-finite preconditioner factor");
 }
 
+// Z(tau, tau)^{-1} of a level-l node on the device (complex FP64 LU); returned column-major
+// on the host.
+static void dense_inverse(hodbf_op &op, rocblas_handle rh, int l, int64_t tau,
+                          std::vector<cd> &Xh, hipStream_t st) {
+  const Tree &t = op.tree;
+  const int32_t lo = t.node_lo(l, tau), hi = t.node_hi(l, tau);
+  const int64_t n = hi - lo;
+  std::vector<EntryJob> jobs;
+  std::vector<int32_t> cols(static_cast<size_t>(n));
+  for (int64_t k = 0; k < n; ++k) cols[size_t(k)] = int32_t(lo + k);
+  for (int64_t c0 = 0; c0 < n; c0 += 64) {
+    const int64_t nc = std::min<int64_t>(64, n - c0);
+    jobs.push_back({c0 * n, lo, int32_t(n), int32_t(c0), int32_t(nc)});
+  }
+  std::vector<cd> eye(size_t(n) * n, cd(0.0, 0.0));
+  for (int64_t i = 0; i < n; ++i) eye[size_t(i) * n + i] = 1.0;
+  DevBuf dj, dc, A, B, piv, info;
+  dj.upload(jobs.data(), jobs.size() * sizeof(EntryJob), st);
+  dc.upload(cols.data(), cols.size() * sizeof(int32_t), st);
+  B.upload(eye.data(), eye.size() * sizeof(cd), st);
+  A.alloc(size_t(n) * n * sizeof(double2));
+  piv.alloc(size_t(n) * sizeof(int64_t));
+  info.alloc(sizeof(int64_t));
+  const double2 k2S = make_double2(op.ker.k2S.real(), op.ker.k2S.imag());
+  launch_entries(dj.as<EntryJob>(), int64_t(jobs.size()), dc.as<int32_t>(), op.dev.xyz.as<short4>(),
+                 op.dev.inv_eps.as<double2>(), op.dev.kappa.as<double2>(), op.ker.kh, k2S, nullptr,
+                 A.as<double2>(), st);
+  HIPCHK(hipGetLastError());
+  rb_check(rocblas_set_stream(rh, st), "rocblas_set_stream");
+  rb_check(rocsolver_zgetrf_64(rh, n, n, A.as<rocblas_double_complex>(), n, piv.as<int64_t>(),
+                               info.as<int64_t>()),
+           "rocsolver_zgetrf_64");
+  int64_t hinfo = 0;
+  HIPCHK(hipMemcpyAsync(&hinfo, info.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (hinfo != 0) fail(HODBF_E_NUMERIC, "singular diagonal block in the preconditioner");
+  rb_check(rocsolver_zgetrs_64(rh, rocblas_operation_none, n, n, A.as<rocblas_double_complex>(), n,
+                               piv.as<int64_t>(), B.as<rocblas_double_complex>(), n),
+           "rocsolver_zgetrs_64");
+  Xh.resize(size_t(n) * n);
+  HIPCHK(hipMemcpyAsync(Xh.data(), B.p, B.bytes, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (auto &v : Xh)
+    if (!std::isfinite(v.real()) || !std::isfinite(v.imag()))
+      fail(HODBF_E_NUMERIC, "non-finite preconditioner factor");
+}
+
 void build_precond(hodbf_op &op, hipStream_t st) {
   auto t0 = std::chrono::steady_clock::now();
   PrecondData &pd = op.pre;
@@ -178,6 +225,13 @@ void build_precond(hodbf_op &op, hipStream_t st) {
   const int LH = t.depth;
   const auto &p = op.params;
   pd.min_level = std::min(p.precond_min_level, LH);
+  // level of the dense diagonal inverses that start the product: the leaves, or, with
+  // precond_dense_levels = d, the level L_H - d nodes (their exact inverses are what the
+  // leaf inverses and the d lowest levels of X_tau compose to)
+  const int dl = std::min(p.precond_dense_levels, LH);
+  const int lb = LH - dl;
+  if (dl > 0 && lb < pd.min_level)
+    fail(HODBF_E_ARG, "precond_dense_levels reaches above precond_min_level");
   const bool want32 = (p.precond_prec & HODBF_P_FP32) != 0;
   const bool wantb16 = (p.precond_prec & HODBF_P_BF16) != 0;
   const bool wanth16 = (p.precond_prec & HODBF_P_FP16) != 0;
@@ -197,51 +251,63 @@ void build_precond(hodbf_op &op, hipStream_t st) {
     *scale = s;
     return off;
   };
-  // leaves: dense inverses (FP64 on the host, 64 x 64)
-  {
-    PackSink pk;
-    pk.table = &pd.table;
-    const int64_t nleaf = int64_t(1) << LH;
-    for (int64_t g = 0; g < nleaf; ++g) {
-      const int32_t lo = t.node_lo(LH, g), hi = t.node_hi(LH, g);
-      const int m = hi - lo;
-      std::vector<cd> Dv(size_t(m) * m);
-      for (int c = 0; c < m; ++c)
-        for (int r = 0; r < m; ++r) Dv[size_t(c) * m + r] = op.ker.entry(lo + r, lo + c);
-      small_inverse(Dv, m);
-      Mat D;
-      D.m = D.n = m;
-      D.v.assign(Dv.begin(), Dv.end());
-      Pair pr{};
-      pr.f_off = put(D, &pr.scale);
-      pr.in_row = lo;
-      pr.n = m;
-      pr.lda = m;
-      pr.in_buf = 0;
-      pk.table->push_back({0, LH, g, 0, 0, 0, 0, 0, m, m, pr.f_off, m});
-      pd.scales.push_back(pr.scale);
-      Seg sg{};
-      sg.m = m;
-      sg.p0 = int32_t(pk.pairs.size());
-      sg.p1 = sg.p0 + 1;
-      sg.map0 = int32_t(pk.rowmap.size());
-      sg.map1 = sg.map0 + 1;
-      pk.rowmap.push_back({0, lo});
-      pk.pairs.push_back(pr);
-      pk.segs.push_back(sg);
-    }
-    pk.launches.push_back({0, int64_t(pk.segs.size()), 0, 1});
-    upload_program(pd.leaf, pk, st);
-  }
   rocblas_handle rh = nullptr;
   rb_check(rocblas_create_handle(&rh), "rocblas_create_handle");
   struct HandleGuard {
     rocblas_handle h;
     ~HandleGuard() { rocblas_destroy_handle(h); }
   } guard{rh};
+  // the first program: dense inverses of the diagonal blocks of the level-lb nodes (the
+  // leaves: FP64 on the host; larger nodes: FP64 LU on the device), each cut into row
+  // tiles of at most kTileRows rows that read the node's whole input range
+  {
+    PackSink pk;
+    pk.table = &pd.table;
+    const int64_t nnode = int64_t(1) << lb;
+    for (int64_t g = 0; g < nnode; ++g) {
+      const int32_t lo = t.node_lo(lb, g), hi = t.node_hi(lb, g);
+      const int m = hi - lo;
+      std::vector<cd> Dv;
+      if (lb == LH) {
+        Dv.resize(size_t(m) * m);
+        for (int c = 0; c < m; ++c)
+          for (int r = 0; r < m; ++r) Dv[size_t(c) * m + r] = op.ker.entry(lo + r, lo + c);
+        small_inverse(Dv, m);
+      } else {
+        dense_inverse(op, rh, lb, g, Dv, st);
+      }
+      Mat D;
+      D.m = D.n = m;
+      D.v.assign(Dv.begin(), Dv.end());
+      float scale = 1.0f;
+      const int64_t off = put(D, &scale);
+      pk.table->push_back({0, lb, g, 0, 0, 0, 0, 0, m, m, off, m});
+      pd.scales.push_back(scale);
+      for (int r0 = 0; r0 < m; r0 += kTileRows) {
+        Pair pr{};
+        pr.f_off = off + r0;
+        pr.in_row = lo;
+        pr.n = m;
+        pr.lda = m;
+        pr.in_buf = 0;
+        pr.scale = scale;
+        Seg sg{};
+        sg.m = std::min(kTileRows, m - r0);
+        sg.p0 = int32_t(pk.pairs.size());
+        sg.p1 = sg.p0 + 1;
+        sg.map0 = int32_t(pk.rowmap.size());
+        sg.map1 = sg.map0 + 1;
+        pk.rowmap.push_back({0, lo + r0});
+        pk.pairs.push_back(pr);
+        pk.segs.push_back(sg);
+      }
+    }
+    pk.launches.push_back({0, int64_t(pk.segs.size()), 0, 1});
+    upload_program(pd.leaf, pk, st);
+  }
   int maxr = 0;
   int64_t ids = 0;
-  for (int l = LH - 1; l >= pd.min_level; --l) {
+  for (int l = lb - 1; l >= pd.min_level; --l) {
     std::vector<Butterfly> bfs;
     for (int64_t tau = 0; tau < (int64_t(1) << l); ++tau) {
       std::vector<cd> Xh;

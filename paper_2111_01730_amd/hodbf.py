@@ -62,11 +62,11 @@ class Operator:
     """A compressed VIE system matrix (and optional preconditioner) resident on the GPU."""
 
     def __init__(self, grid, tol_con=1e-4, tol_fact=0.0, leaf_size=64, precond=P_NONE,
-                 precond_min_level=0, seed=1, hbm_budget=0):
+                 precond_min_level=0, seed=1, hbm_budget=0, precond_dense_levels=0):
         self.grid = grid
         self.n = grid.n
         p = _lib.make_params(grid, tol_con, tol_fact, leaf_size, precond, precond_min_level,
-                             seed, hbm_budget, _stream())
+                             seed, hbm_budget, _stream(), precond_dense_levels)
         h = C.c_void_p()
         check(lib().hodbf_build(C.byref(p), C.byref(h)))
         self._h = h

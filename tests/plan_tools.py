@@ -122,13 +122,40 @@ def hodbf_from_export(grid, perm, table, vals, skel=None):
     return HODBF(tree, D, bf)
 
 
+class DenseBottomPrecond(Precond):
+    """The multiplicative form started from the exported dense inverses of the level-lb
+    nodes' diagonal blocks (the library's precond_dense_levels = L_H - lb), then the X_tau
+    of the levels above, applied in FP64 like the oracle's own form."""
+
+    def __init__(self, tree, lb, Dinv, X):
+        super().__init__(tree, Dinv, X)
+        self.lb = lb
+
+    def apply_tree(self, xt):
+        tr = self.tree
+        z = np.empty_like(xt, dtype=np.complex128)
+        for i, (lo, hi) in enumerate(tr.ranges[self.lb]):
+            z[lo:hi] = self.Dinv[i] @ xt[lo:hi]
+        for l in range(self.lb - 1, -1, -1):
+            for i in range(1 << l):
+                blocks = self.X[(l, i)]
+                c = [tr.node(l + 1, 2 * i), tr.node(l + 1, 2 * i + 1)]
+                zc = [z[lo:hi].copy() for (lo, hi) in c]
+                for a in range(2):
+                    lo, hi = c[a]
+                    z[lo:hi] += blocks[a][0].apply(zc[0]) + blocks[a][1].apply(zc[1])
+        return z
+
+
 def precond_from_export(grid, perm, table, vals, depth):
     tree = tree_from_perm(perm, grid.n, depth)
     LH = tree.depth
-    Dinv = [None] * (1 << LH)
-    for row in table:
-        if int(row[0]) == 0:
-            Dinv[int(row[2])] = _mat(vals, int(row[10]), int(row[8]), int(row[9]), int(row[11]))
+    dense = [row for row in table if int(row[0]) == 0]
+    lb = int(dense[0][1])  # level of the dense inverses (L_H: the leaves)
+    Dinv = [None] * (1 << lb)
+    for row in dense:
+        assert int(row[1]) == lb
+        Dinv[int(row[2])] = _mat(vals, int(row[10]), int(row[8]), int(row[9]), int(row[11]))
     groups = butterflies_from_table(tree, table, vals, precond=True)
     X = {}
     levels = sorted({k[0] for k in groups})
@@ -148,4 +175,4 @@ def precond_from_export(grid, perm, table, vals, depth):
                 blocks.append(row)
             X[(l, i)] = blocks
     del levels
-    return Precond(tree, Dinv, X)
+    return Precond(tree, Dinv, X) if lb == LH else DenseBottomPrecond(tree, lb, Dinv, X)

@@ -137,3 +137,79 @@ def test_split_bf16_apply_is_reproducible_and_batch_independent(case):
     x2, i2 = op.solve(b, tol=1e-5, use_precond="fp32_split")
     assert np.array_equal(i1["iters"], i2["iters"])
     assert torch.equal(x1, x2)
+
+
+@pytest.fixture(scope="module")
+def dense_case(case):
+    """The same scatterer with the two lowest tree levels (and the leaves) replaced by
+    dense inverses of the level L_H - 2 nodes' diagonal blocks."""
+    from paper_2111_01730_amd import hodbf
+    c, g, op, Z = case
+    print("[precond build 10x9x8 chi_fact=1e-2, dense bottom 2 levels]", flush=True)
+    opd = hodbf.Operator(g, tol_con=1e-4, tol_fact=1e-2, precond=hodbf.P_FP32,
+                         precond_dense_levels=2)
+    return c, g, opd, Z
+
+
+@pytest.mark.parametrize("which,tol", [(2, 2e-5), (6, 128 * 2e-5)])
+def test_dense_bottom_matches_exported_factors(dense_case, which, tol):
+    from tests.plan_tools import DenseBottomPrecond, precond_from_export
+    c, g, op, Z = dense_case
+    LH = op.stats()["levels"]
+    table, vals = op.precond_blocks("fp32")
+    ref = precond_from_export(g, op.perm(), table, vals, LH)
+    assert isinstance(ref, DenseBottomPrecond) and ref.lb == LH - 2
+    x = c["x"][:, :8].astype(np.complex64).astype(np.complex128)
+    z = _apply_copy(op, x, which)
+    err = _rel(z, ref.apply(x))
+    print(f"[dense bottom which {which}: max rel err {err.max():.2e}]", flush=True)
+    assert np.all(err <= tol), err
+    # each dense block is the inverse of its node's diagonal block of the exact Z
+    tree = ref.tree
+    for i, (lo, hi) in enumerate(tree.ranges[ref.lb]):
+        idx = tree.perm[lo:hi]
+        blk = Z[np.ix_(idx, idx)]
+        e = np.linalg.norm(ref.Dinv[i] @ blk - np.eye(hi - lo)) / np.sqrt(hi - lo)
+        assert e <= 1e-4, (i, e)
+
+
+def test_dense_bottom_at_the_root_is_the_inverse(case):
+    # d = L_H: one dense block, the inverse of the whole (uncompressed) Z, stored in FP32
+    from paper_2111_01730_amd import hodbf
+    c, g, op, Z = case
+    LH = op.stats()["levels"]
+    opr = hodbf.Operator(g, tol_con=1e-4, tol_fact=1e-2, precond=hodbf.P_FP32,
+                         precond_dense_levels=LH)
+    x = c["x"][:, :4]
+    z = _apply_copy(opr, (Z @ x).astype(np.complex64).astype(np.complex128), 2)
+    err = _rel(z, x)
+    print(f"[dense root: ||P Z x - x|| / ||x|| = {err.max():.2e}]", flush=True)
+    assert np.all(err <= 1e-4), err
+    b = opr.plane_wave(c["dirs"][:2])
+    xs, info = opr.solve(b, tol=1e-5, use_precond="fp32")
+    assert info["converged"].all() and info["iters"].max() <= 3, info
+
+
+def test_dense_bottom_solve(dense_case, case):
+    c, g, op, Z = dense_case
+    b = op.plane_wave(c["dirs"])
+    out = {}
+    for mode in ("fp32", "fp32_split"):
+        x, info = op.solve(b, tol=1e-5, restart=20, max_iter=500, use_precond=mode)
+        assert info["converged"].all(), (mode, info)
+        assert np.all(_rel(Z @ x.cpu().numpy(), b.cpu().numpy()) <= 1e-5 + 1e-3)
+        out[mode] = info["iters"]
+    # exact bottom levels: no more steps than with the compressed ones
+    _, ileaf = case[2].solve(b, tol=1e-5, restart=20, max_iter=500, use_precond="fp32")
+    print(f"[dense bottom steps {out['fp32'].max()} vs leaves {ileaf['iters'].max()}]", flush=True)
+    assert out["fp32"].max() <= ileaf["iters"].max()
+
+
+def test_dense_bottom_reaching_above_min_level_is_rejected(case):
+    from paper_2111_01730_amd import hodbf
+    from paper_2111_01730_amd._lib import HodbfError
+    c, g, op, Z = case
+    LH = op.stats()["levels"]
+    with pytest.raises(HodbfError):
+        hodbf.Operator(g, tol_con=1e-4, tol_fact=1e-2, precond=hodbf.P_FP32,
+                       precond_min_level=LH - 1, precond_dense_levels=2)

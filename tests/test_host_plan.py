@@ -74,7 +74,8 @@ def test_free_space_plan_has_zero_ranks():
 
 @pytest.mark.parametrize("field,value", [("nx", 0), ("h", 0.0), ("h", -1.0), ("k0", 0.0),
                                          ("tol_con", 0.0), ("tol_con", 1.5), ("leaf_size", 0),
-                                         ("leaf_size", 65)])
+                                         ("leaf_size", 65), ("precond_min_level", -1),
+                                         ("precond_dense_levels", -1)])
 def test_argument_errors(field, value):
     g = make_grid(4, 4, 4, 0.1, 2.0)
     p = _lib.make_params(g, 1e-4)
