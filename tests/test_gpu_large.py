@@ -77,10 +77,12 @@ def test_c5_slabs_128_preconditioned_solve():
     max_iter = int(os.environ.get("HODBF_C5_MAX_ITER", "2500"))
     tol_fact = float(os.environ.get("HODBF_C5_TOL_FACT", "1e-4"))
     restart = int(os.environ.get("HODBF_C5_RESTART", "100"))
+    dense = int(os.environ.get("HODBF_C5_DENSE_LEVELS", "0"))
+    arith = os.environ.get("HODBF_C5_PRECOND", "fp32")  # or fp32_split (the mixed form)
     print(f"[c5 solve: build N={g.n}, preconditioner levels >= {lmin}, chi_fact {tol_fact}, "
-          f"restart {restart}]", flush=True)
+          f"dense levels {dense}, {arith} arithmetic, restart {restart}]", flush=True)
     op = Operator(g, tol_con=tol, tol_fact=tol_fact, precond=P_FP32, precond_min_level=lmin,
-                  seed=cfg["seed"])
+                  seed=cfg["seed"], precond_dense_levels=dense)
     st = op.stats()
     print(f"[c5 solve: forward {st['build_seconds']:.0f} s, preconditioner "
           f"{st['precond_seconds']:.0f} s, {st['bytes_total'] / 2**30:.1f} GiB]", flush=True)
@@ -88,7 +90,7 @@ def test_c5_slabs_128_preconditioned_solve():
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    x, info = op.solve(b, tol=tol, restart=restart, max_iter=max_iter, use_precond="fp32")
+    x, info = op.solve(b, tol=tol, restart=restart, max_iter=max_iter, use_precond=arith)
     e1.record()
     torch.cuda.synchronize()
     print(f"[c5 solve: {e0.elapsed_time(e1) / 1e3:.1f} s, steps mean "
