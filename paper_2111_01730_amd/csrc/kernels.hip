@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <cstdlib>
+#include <type_traits>
 
 #include "device.h"
 
@@ -260,7 +261,7 @@ __device__ __forceinline__ unsigned load_chunk(const ChunkSrc &c, int kb, const 
     const int e = tid + kThreads * i;
     const int hi = kb + (e >> 6), lo = e & 63;  // input row hi, column lo
     const unsigned off = unsigned(min(hi, c.n - 1)) * unsigned(R) + unsigned(min(lo, c.rc - 1));
-    xr[i] = ldg_f2(xb, off);
+    xr[i] = ldg_f2_sb(xb, off * 8u);
     msk |= unsigned(hi < c.n && lo < c.rc) << i;
   }
 #pragma unroll
@@ -268,7 +269,10 @@ __device__ __forceinline__ unsigned load_chunk(const ChunkSrc &c, int kb, const 
     const int e = tid + kThreads * i;
     const int hi = kb + e / kTileRows, lo = e % kTileRows;  // factor column hi, row lo
     const unsigned off = unsigned(min(hi, c.n - 1)) * unsigned(c.lda) + unsigned(min(lo, c.m - 1));
-    ar[i] = load_factor(ab, off);
+    if constexpr (std::is_same<FT, float2>::value)
+      ar[i] = ldg_f2_sb(ab, off * 8u);
+    else
+      ar[i] = load_factor(ab, off);
     msk |= unsigned(hi < c.n && lo < c.m) << (kXL + i);
   }
   return msk;
