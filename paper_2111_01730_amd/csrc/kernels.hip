@@ -537,7 +537,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
 // Split-BF16 arithmetic for complex FP32 factors and inputs.  Each FP32 value v is
 // written as hi + lo with hi = bf16(v) and lo = bf16(v - hi), both rounded to nearest
 // even, so |v - hi - lo| <= 2^-18 |v|; a product a x is taken as
-// hi_a hi_x + hi_a lo_x + lo_a hi_x (the dropped lo_a lo_x is below 2^-17 |a x|) on
+// hi_a hi_x + hi_a lo_x + lo_a hi_x (the dropped lo_a lo_x is below 2^-18 |a x|) on
 // v_mfma_f32_16x16x32_bf16 with FP32 accumulation.  One MFMA consumes a whole chunk of
 // 16 complex columns (32 real K), against eight FP32 16x16x4 MFMAs of four times the
 // cycles each: the same tiles, work items and chunk pipeline as tile_item, with the
@@ -548,8 +548,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
 // order).  Slots 2 v, 2 v + 1 are (Re, Im) of complex column 4 kk + v: for the factor
 // that is the stored pair itself, for the input of output column 2 q it is (xr, -xi) and
 // of column 2 q + 1 it is (xi, xr).  LDS holds the factor chunk row-major and the input
-// chunk column-major in both forms, each complex value as (hi pair, lo pair), so a
-// fragment is two 16-byte reads.
+// chunk column-major in both forms, in the planes described below.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
 typedef float floatx2v __attribute__((ext_vector_type(2)));
