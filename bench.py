@@ -42,11 +42,11 @@ PEAK_BF16_MFMA_TFLOPS = 2500.0
 # the rocSOLVER factorisations of the preconditioner's construction; the same kernel on
 # the forward operator (profiles/grouped_mfma_s3_forward_c2_r64_traffic.md) moves the
 # same bytes as the FP32 kernel, 1.16x its algorithmic bytes.
-MEASURED_TRAFFIC = {"sources_sha256": "e3c2d291fe8558b4352a3843d03eddda66df997593cf578ca9a526adb87f3b7c",
+MEASURED_TRAFFIC = {"sources_sha256": "7322aeba1294581260cd167acbc7a803d8f4938e930e3fefa28ce9ac6d904c9d",
                     "precond_s3": {"bytes_per_apply": None, "launches_per_apply": 55},
-                    "forward_f32": {"bytes_per_apply": 1317482834.7 + 435991248.0,
+                    "forward_f32": {"bytes_per_apply": 1317051665.7 + 435898304.0,
                                     "launches_per_apply": 10},
-                    "forward_s3": {"bytes_per_apply": 1315883952.3 + 435857680.0,
+                    "forward_s3": {"bytes_per_apply": 1315968014.7 + 435858896.0,
                                    "launches_per_apply": 10}}
 
 
