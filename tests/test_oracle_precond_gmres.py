@@ -79,3 +79,32 @@ def test_preconditioned_compressed_solve(case):
     assert conv
     # true residual against the exact operator stays within chi_sol + O(10 chi_con)
     assert np.linalg.norm(Z @ x - b) <= (1e-4 + 1e-3) * np.linalg.norm(b)
+
+
+def test_lowest_levels_compose_to_node_inverses(case):
+    # Algorithm 1's leaf inverses followed by the uncompressed X_tau of the levels >= lb
+    # equal the inverses of the diagonal blocks Z(tau, tau) of the level-lb nodes (each
+    # level's I + X_tau = Z(tau, tau)^-1 diag(Z(tau1, tau1), Z(tau2, tau2)) telescopes):
+    # the identity behind storing those node inverses directly (precond_dense_levels)
+    c, g, Z = case
+    p = precond.build_precond(g, 0.1, compress=False)
+    tr = p.tree
+    lb = tr.depth - 2
+    X = {}
+    for (l, i), blocks in p.X.items():
+        if l >= lb:
+            X[(l, i)] = blocks
+        else:
+            X[(l, i)] = [[precond.DenseBlock(np.zeros((ha - la, hb - lb_), dtype=complex))
+                          for (lb_, hb) in (tr.node(l + 1, 2 * i), tr.node(l + 1, 2 * i + 1))]
+                         for (la, ha) in (tr.node(l + 1, 2 * i), tr.node(l + 1, 2 * i + 1))]
+    q = precond.Precond(tr, p.Dinv, X)
+    xt = c["x"][:, :3][tr.perm]
+    zt = q.apply_tree(xt)
+    Zt = Z[np.ix_(tr.perm, tr.perm)]
+    assert len(tr.ranges[lb]) == 1 << lb
+    for (lo, hi) in tr.ranges[lb]:
+        ref = np.linalg.solve(Zt[lo:hi, lo:hi], xt[lo:hi])
+        assert np.linalg.norm(zt[lo:hi] - ref) <= 1e-11 * np.linalg.norm(ref)
+    # and the product is not already the full inverse (the levels above lb still couple)
+    assert np.linalg.norm(Zt @ zt - xt) > 1e-3 * np.linalg.norm(xt)
