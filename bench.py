@@ -383,7 +383,7 @@ def main():
         print(json.dumps(oracle_mode(args)))
         return 0
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "hodbf runs on one GPU (multi-GPU sharding is a design, not built); --gpus must be 1",
                           "n_gpus": args.gpus}))
         return 2
 
