@@ -228,8 +228,8 @@ const char *hodbf_last_error(void);
  * arenas used on any stream.  release(ptr, ctx) returns it; stream-ordered reuse is the
  * allocator's business (scratch is released after the call's last use was enqueued on
  * its stream).  Operator arenas remember the hook they were allocated with; per-call
- * workspace uses the hook installed when the call runs, so change it only while no
- * call is running.  alloc == NULL restores hipMalloc / hipMallocAsync.  The dense
+ * workspace comes from the hook installed when the call starts and goes back to it,
+ * also when the call fails; change the hook only while no call is running.  alloc == NULL restores hipMalloc / hipMallocAsync.  The dense
  * factorisations of the preconditioner construction keep their own rocSOLVER
  * temporaries.  E_ARG if alloc is set and release is not.  Process-wide, thread-safe.
  */

@@ -110,23 +110,22 @@ void DevBuf::upload(const void *src, size_t nbytes, hipStream_t st) {
   }
 }
 
-void *scratch_alloc(size_t bytes, hipStream_t st) {
-  void *p = nullptr;
+Scratch::Scratch(size_t bytes, hipStream_t st) : st_(st) {
   if (bytes == 0) bytes = 256;
   const AllocHook h = current_hook();
   if (h.alloc) {
-    p = h.alloc(bytes, st, h.ctx);
-    if (!p) fail(HODBF_E_NOMEM, "allocator hook returned NULL");
+    p_ = h.alloc(bytes, st, h.ctx);
+    if (!p_) fail(HODBF_E_NOMEM, "allocator hook returned NULL");
+    release_ = h.release;
+    ctx_ = h.ctx;
   } else {
-    HIPCHK(hipMallocAsync(&p, bytes, st));
+    HIPCHK(hipMallocAsync(&p_, bytes, st));
   }
-  return p;
 }
-void scratch_free(void *p, hipStream_t st) {
-  if (!p) return;
-  const AllocHook h = current_hook();
-  if (h.alloc) h.release(p, h.ctx);
-  else (void)hipFreeAsync(p, st);
+Scratch::~Scratch() {
+  if (!p_) return;
+  if (release_) release_(p_, ctx_);
+  else (void)hipFreeAsync(p_, st_);
 }
 
 
@@ -314,7 +313,8 @@ hodbf_status hodbf_apply(const hodbf_op *op, int32_t nrhs, hodbf_dtype dtype, co
     const int64_t n = op->n;
     const size_t vbytes = size_t(n) * nrhs * sizeof(float2);
     const size_t wbytes = size_t(forward_work_rows(*op)) * nrhs * sizeof(float2);
-    char *buf = static_cast<char *>(scratch_alloc(2 * vbytes + wbytes, st));
+    const Scratch scr(2 * vbytes + wbytes, st);
+    char *buf = scr.as<char>();
     float2 *xt = reinterpret_cast<float2 *>(buf);
     float2 *yt = reinterpret_cast<float2 *>(buf + vbytes);
     float2 *wk = reinterpret_cast<float2 *>(buf + 2 * vbytes);
@@ -323,7 +323,6 @@ hodbf_status hodbf_apply(const hodbf_op *op, int32_t nrhs, hodbf_dtype dtype, co
     apply_forward_tree(*op, xt, yt, wk, nrhs, st);
     launch_scatter(yt, false, y, c128, ldy, op->dev.perm.as<int32_t>(), n, nrhs, st);
     HIPCHK(hipGetLastError());
-    scratch_free(buf, st);
   });
 }
 
@@ -338,7 +337,8 @@ hodbf_status hodbf_precond_apply(const hodbf_op *op, int32_t nrhs, hodbf_dtype d
     const int64_t n = op->n;
     const size_t vbytes = size_t(n) * nrhs * sizeof(float2);
     const size_t wbytes = size_t(precond_work_rows(*op)) * nrhs * sizeof(float2);
-    char *buf = static_cast<char *>(scratch_alloc(2 * vbytes + wbytes, st));
+    const Scratch scr(2 * vbytes + wbytes, st);
+    char *buf = scr.as<char>();
     float2 *xt = reinterpret_cast<float2 *>(buf);
     float2 *zt = reinterpret_cast<float2 *>(buf + vbytes);
     float2 *wk = reinterpret_cast<float2 *>(buf + 2 * vbytes);
@@ -347,7 +347,6 @@ hodbf_status hodbf_precond_apply(const hodbf_op *op, int32_t nrhs, hodbf_dtype d
     apply_precond_tree(*op, op->pre.default_ft, xt, zt, wk, nrhs, st);
     launch_scatter(zt, false, y, c128, ldy, op->dev.perm.as<int32_t>(), n, nrhs, st);
     HIPCHK(hipGetLastError());
-    scratch_free(buf, st);
   });
 }
 
@@ -373,14 +372,14 @@ hodbf_status hodbf_apply_tree(const hodbf_op *op, int32_t which, int32_t nrhs, c
       if (ft == FT_F16 && !op->pre.F16.p) fail(HODBF_E_STATE, "no FP16 preconditioner copy");
     }
     const int64_t rows = fwd ? forward_work_rows(*op) : precond_work_rows(*op);
-    float2 *wk = static_cast<float2 *>(scratch_alloc(size_t(std::max<int64_t>(rows, 1)) * nrhs * 8, st));
+    const Scratch scr(size_t(std::max<int64_t>(rows, 1)) * nrhs * 8, st);
+    float2 *wk = scr.as<float2>();
     if (fwd)
       apply_forward_tree(*op, static_cast<const float2 *>(x), static_cast<float2 *>(y), wk, nrhs, st,
                          ft);
     else
       apply_precond_tree(*op, ft, static_cast<const float2 *>(x), static_cast<float2 *>(y), wk, nrhs, st);
     HIPCHK(hipGetLastError());
-    scratch_free(wk, st);
   });
 }
 
@@ -393,13 +392,13 @@ hodbf_status hodbf_plane_wave(const hodbf_op *op, int32_t nrhs, const double *di
     for (int i = 0; i < 3 * nrhs; ++i)
       if (!std::isfinite(dirs[i])) fail(HODBF_E_ARG, "non-finite direction");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    double *dd = static_cast<double *>(scratch_alloc(sizeof(double) * 3 * nrhs, st));
+    const Scratch scr(sizeof(double) * 3 * nrhs, st);
+    double *dd = scr.as<double>();
     HIPCHK(hipMemcpyAsync(dd, dirs, sizeof(double) * 3 * nrhs, hipMemcpyHostToDevice, st));
     const auto &p = op->params;
     launch_plane_wave(dd, nrhs, p.nx, p.ny, p.nz, p.h, p.k0, static_cast<double2 *>(b), ldb, st);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(st));
-    scratch_free(dd, st);
   });
 }
 

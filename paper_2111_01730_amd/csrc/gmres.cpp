@@ -80,8 +80,8 @@ static void solve_impl(const hodbf_op &op, int R, const void *b, int64_t ldb, vo
   add(size_t(R) * 16);                              // sq
   add(size_t(R) * 8 * 2);                           // bnorm, est
   add(size_t(R) * 4 * 2);                           // jend, active
-  char *base = static_cast<char *>(scratch_alloc(need, st));
-  Carve cv{base};
+  const Scratch scr(need, st);
+  Carve cv{scr.as<char>()};
   double2 *bt = cv.take<double2>(NR), *xt = cv.take<double2>(NR);
   double2 *rt = cv.take<double2>(NR), *xc = cv.take<double2>(NR);
   void *stage = cv.take<double2>(size_t(std::max<int64_t>(n, int64_t(m + 1) * m)) * R);
@@ -121,6 +121,11 @@ static void solve_impl(const hodbf_op &op, int R, const void *b, int64_t ldb, vo
   // Host-to-device copies of small host vectors: the source is kept alive until the solve
   // returns, so its lifetime never depends on when the asynchronous copy reads it.
   std::deque<std::vector<char>> held;
+  // On every exit, normal or by error, the stream drains before `held` is released.
+  struct DrainOnExit {
+    hipStream_t st;
+    ~DrainOnExit() { (void)hipStreamSynchronize(st); }
+  } drain{st};
   auto upload = [&](void *dst, const void *src, size_t bytes) {
     if (bytes == 0) return;
     held.emplace_back(static_cast<const char *>(src), static_cast<const char *>(src) + bytes);
@@ -303,7 +308,6 @@ static void solve_impl(const hodbf_op &op, int R, const void *b, int64_t ldb, vo
   launch_scatter(xt, true, x, true, ldx, perm, n, R, st);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));
-  scratch_free(base, st);
   bool allconv = true;
   for (int q = 0; q < R; ++q) {
     const bool c = bnorm[size_t(q)] == 0 || relres[size_t(q)] <= o.tol;

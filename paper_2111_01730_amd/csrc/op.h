@@ -137,9 +137,24 @@ void apply_precond_tree(const hodbf_op &op, int ftype, const float2 *x, float2 *
                         int R, hipStream_t st);
 int64_t precond_work_rows(const hodbf_op &op);
 
-// Stream-ordered scratch allocation.
-void *scratch_alloc(size_t bytes, hipStream_t st);
-void scratch_free(void *p, hipStream_t st);
+// One stream-ordered scratch allocation owned by a scope: it comes from the allocator
+// hook installed at construction (else hipMallocAsync) and goes back to that same
+// allocator when the scope ends, also when an error unwinds it.
+class Scratch {
+ public:
+  Scratch(size_t bytes, hipStream_t st);
+  ~Scratch();
+  Scratch(const Scratch &) = delete;
+  Scratch &operator=(const Scratch &) = delete;
+  template <typename T>
+  T *as() const { return static_cast<T *>(p_); }
+
+ private:
+  void *p_ = nullptr;
+  hipStream_t st_;
+  hodbf_free_fn release_ = nullptr;
+  void *ctx_ = nullptr;
+};
 
 void build_precond(hodbf_op &op, hipStream_t st);
 
