@@ -170,6 +170,16 @@ hodbf_status vie_solve(const hodbf_op *op, int32_t nrhs, const void *b, int64_t 
                        hodbf_solve_info *info, void *stream);
 
 /*
+ * hodbf_solve_workspace -- *bytes = the device memory one vie_solve with these
+ * arguments allocates for its own use (Krylov basis, preconditioned basis, vectors,
+ * apply workspace, reductions), for admission by memory budget.  The caller's b and x
+ * are not included.  0 for nrhs = 0.  Same argument errors as vie_solve (E_ARG,
+ * E_STATE for a preconditioner copy the operator lacks); touches no GPU.
+ */
+hodbf_status hodbf_solve_workspace(const hodbf_op *op, int32_t nrhs,
+                                   const hodbf_solve_opts *opts, size_t *bytes);
+
+/*
  * hodbf_plane_wave -- b(:, q) = exp(-j k0 dhat_q . (r - r_c)) at the voxel centres
  * r = h (i + 1/2), r_c the box centre (the plane-wave excitation of Section IV).
  * dirs: HOST, 3*nrhs doubles (unit vectors).  b: complex FP64 DEVICE, ld >= N.

@@ -16,7 +16,7 @@ C64, C128 = 0, 1
 P_NONE, P_FP32, P_BF16, P_BOTH, P_FP16 = 0, 1, 2, 3, 4
 
 EXPORTED = ["hodbf_build", "hodbf_apply", "hodbf_precond_apply", "vie_solve", "hodbf_plane_wave",
-            "hodbf_apply_tree",
+            "hodbf_apply_tree", "hodbf_solve_workspace",
             "hodbf_stats", "hodbf_export", "hodbf_free", "hodbf_last_error", "hodbf_plan_probe",
             "hodbf_set_allocator"]
 
@@ -79,6 +79,7 @@ def lib():
     L.hodbf_precond_apply.argtypes = [vp, i32, i32, vp, i64, vp, i64, vp]
     L.vie_solve.argtypes = [vp, i32, vp, i64, vp, i64, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
     L.hodbf_plane_wave.argtypes = [vp, i32, C.POINTER(C.c_double), vp, i64, vp]
+    L.hodbf_solve_workspace.argtypes = [vp, i32, C.POINTER(SolveOpts), C.POINTER(C.c_size_t)]
     L.hodbf_stats.argtypes = [vp, C.POINTER(Stats)]
     L.hodbf_export.argtypes = [vp, i32, vp, C.POINTER(C.c_size_t)]
     L.hodbf_plan_probe.argtypes = [C.POINTER(BuildParams), i32, vp, C.POINTER(C.c_size_t)]
@@ -88,7 +89,7 @@ def lib():
     L.hodbf_free.restype = None
     L.hodbf_last_error.restype = C.c_char_p
     for name in ["hodbf_build", "hodbf_apply", "hodbf_precond_apply", "vie_solve", "hodbf_apply_tree",
-                 "hodbf_plane_wave", "hodbf_stats", "hodbf_export", "hodbf_plan_probe",
+                 "hodbf_plane_wave", "hodbf_solve_workspace", "hodbf_stats", "hodbf_export", "hodbf_plan_probe",
                  "hodbf_set_allocator"]:
         getattr(L, name).restype = C.c_int
     _lib = L

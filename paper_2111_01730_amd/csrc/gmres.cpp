@@ -29,34 +29,39 @@ struct Carve {
 
 }  // namespace
 
-static void solve_impl(const hodbf_op &op, int R, const void *b, int64_t ldb, void *x,
-                       int64_t ldx, const hodbf_solve_opts &o, hodbf_solve_info *info,
-                       hipStream_t st, hodbf_status &status) {
-  const int64_t n = op.n;
-  const int m = o.restart;
-  int pre_ft = -1;
-  if (o.use_precond == 1) {
+// Arithmetic of the preconditioner products selected by use_precond (-1: none).
+static int precond_ftype(const hodbf_op &op, int use_precond) {
+  if (use_precond == 0) return -1;
+  if (use_precond == 1) {
     if (!op.pre.present) fail(HODBF_E_STATE, "operator has no preconditioner");
-    pre_ft = op.pre.default_ft;
-  } else if (o.use_precond == 8 + HODBF_P_FP32) {
-    if (!op.pre.F32.p) fail(HODBF_E_STATE, "no FP32 preconditioner copy");
-    pre_ft = FT_C64;
-  } else if (o.use_precond == 16 + HODBF_P_FP32) {
-    if (!op.pre.F32.p) fail(HODBF_E_STATE, "no FP32 preconditioner copy");
-    pre_ft = FT_C64_S3;
-  } else if (o.use_precond == 8 + HODBF_P_BF16) {
-    if (!op.pre.BF16.p) fail(HODBF_E_STATE, "no BF16 preconditioner copy");
-    pre_ft = FT_BF16;
-  } else if (o.use_precond == 8 + HODBF_P_FP16) {
-    if (!op.pre.F16.p) fail(HODBF_E_STATE, "no FP16 preconditioner copy");
-    pre_ft = FT_F16;
-  } else if (o.use_precond != 0) {
-    fail(HODBF_E_ARG, "unknown use_precond");
+    return op.pre.default_ft;
   }
+  if (use_precond == 8 + HODBF_P_FP32) {
+    if (!op.pre.F32.p) fail(HODBF_E_STATE, "no FP32 preconditioner copy");
+    return FT_C64;
+  }
+  if (use_precond == 16 + HODBF_P_FP32) {
+    if (!op.pre.F32.p) fail(HODBF_E_STATE, "no FP32 preconditioner copy");
+    return FT_C64_S3;
+  }
+  if (use_precond == 8 + HODBF_P_BF16) {
+    if (!op.pre.BF16.p) fail(HODBF_E_STATE, "no BF16 preconditioner copy");
+    return FT_BF16;
+  }
+  if (use_precond == 8 + HODBF_P_FP16) {
+    if (!op.pre.F16.p) fail(HODBF_E_STATE, "no FP16 preconditioner copy");
+    return FT_F16;
+  }
+  fail(HODBF_E_ARG, "unknown use_precond");
+}
+
+// Device workspace of one solve: every buffer solve_impl carves, each rounded up to 256
+// bytes plus 256 of alignment slack.
+static size_t solve_workspace(const hodbf_op &op, int R, int m, bool pre) {
+  const int64_t n = op.n;
   const int64_t NR = n * R;
   const int nblk = multidot_blocks(n, R);
-  const int64_t wrows = std::max(forward_work_rows(op), pre_ft >= 0 ? precond_work_rows(op) : 0);
-  // workspace sizing (bytes, with alignment slack)
+  const int64_t wrows = std::max(forward_work_rows(op), pre ? precond_work_rows(op) : 0);
   size_t need = 0;
   auto add = [&](size_t b) { need += ((b + 255) & ~size_t(255)) + 256; };
   add(NR * 16);                 // bt
@@ -80,7 +85,20 @@ static void solve_impl(const hodbf_op &op, int R, const void *b, int64_t ldb, vo
   add(size_t(R) * 16);                              // sq
   add(size_t(R) * 8 * 2);                           // bnorm, est
   add(size_t(R) * 4 * 2);                           // jend, active
-  const Scratch scr(need, st);
+  return need;
+}
+
+static void solve_impl(const hodbf_op &op, int R, const void *b, int64_t ldb, void *x,
+                       int64_t ldx, const hodbf_solve_opts &o, hodbf_solve_info *info,
+                       hipStream_t st, hodbf_status &status) {
+  const int64_t n = op.n;
+  const int m = o.restart;
+  const int pre_ft = precond_ftype(op, o.use_precond);
+  const int64_t NR = n * R;
+  const int nblk = multidot_blocks(n, R);
+  const int64_t wrows = std::max(forward_work_rows(op), pre_ft >= 0 ? precond_work_rows(op) : 0);
+  const size_t ws = solve_workspace(op, R, m, pre_ft >= 0);
+  const Scratch scr(ws, st);
   Carve cv{scr.as<char>()};
   double2 *bt = cv.take<double2>(NR), *xt = cv.take<double2>(NR);
   double2 *rt = cv.take<double2>(NR), *xc = cv.take<double2>(NR);
@@ -106,6 +124,7 @@ static void solve_impl(const hodbf_op &op, int R, const void *b, int64_t ldb, vo
   gs.est = cv.take<double>(R);
   gs.jend = cv.take<int32_t>(R);
   gs.active = cv.take<int32_t>(R);
+  if (cv.off > ws) fail(HODBF_E_HIP, "internal: solve buffers exceed the sized workspace");
 
   const int32_t *perm = op.dev.perm.as<int32_t>();
   auto norms2 = [&](const double2 *v, std::vector<double> &out) {
@@ -326,17 +345,38 @@ static void solve_impl(const hodbf_op &op, int R, const void *b, int64_t ldb, vo
 
 using namespace hodbf;
 
+static void check_solve_args(const hodbf_op *op, int32_t nrhs, const hodbf_solve_opts *opts) {
+  if (!op || !opts) fail(HODBF_E_ARG, "NULL argument");
+  if (nrhs < 0) fail(HODBF_E_ARG, "nrhs < 0");
+  if (!(opts->tol > 0) || opts->restart < 1 || opts->restart > 200 || opts->max_iter < 1)
+    fail(HODBF_E_ARG, "bad solve options");
+}
+
+extern "C" hodbf_status hodbf_solve_workspace(const hodbf_op *op, int32_t nrhs,
+                                              const hodbf_solve_opts *opts, size_t *bytes) {
+  try {
+    if (!bytes) fail(HODBF_E_ARG, "NULL argument");
+    check_solve_args(op, nrhs, opts);
+    const int pre_ft = precond_ftype(*op, opts->use_precond);
+    *bytes = nrhs == 0 ? 0 : solve_workspace(*op, nrhs, opts->restart, pre_ft >= 0);
+    return HODBF_OK;
+  } catch (const Error &e) {
+    set_last_error(e.msg);
+    return e.code;
+  } catch (...) {
+    set_last_error("internal error in hodbf_solve_workspace");
+    return HODBF_E_HIP;
+  }
+}
+
 extern "C" hodbf_status vie_solve(const hodbf_op *op, int32_t nrhs, const void *b, int64_t ldb,
                                   void *x, int64_t ldx, const hodbf_solve_opts *opts,
                                   hodbf_solve_info *info, void *stream) {
   hodbf_status result = HODBF_OK;
   try {
-    if (!op || !opts) fail(HODBF_E_ARG, "NULL argument");
-    if (nrhs < 0) fail(HODBF_E_ARG, "nrhs < 0");
+    check_solve_args(op, nrhs, opts);
     if (nrhs == 0) return HODBF_OK;
     if (!b || !x || ldb < op->n || ldx < op->n) fail(HODBF_E_ARG, "bad b / x / leading dimension");
-    if (!(opts->tol > 0) || opts->restart < 1 || opts->restart > 200 || opts->max_iter < 1)
-      fail(HODBF_E_ARG, "bad solve options");
     solve_impl(*op, nrhs, b, ldb, x, ldx, *opts, info, static_cast<hipStream_t>(stream), result);
     if (result == HODBF_E_NOCONV) set_last_error("GMRES reached max_iter before tol");
     return result;

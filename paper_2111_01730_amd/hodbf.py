@@ -119,6 +119,20 @@ class Operator:
                                      C.c_void_p(b.data_ptr()), self.n, _stream()))
         return b.t()
 
+    @staticmethod
+    def _solve_opts(tol, restart, max_iter, use_precond):
+        up = {"fp32": 8 + P_FP32, "bf16": 8 + P_BF16, "fp16": 8 + P_FP16,
+              "fp32_split": 16 + P_FP32}.get(use_precond, use_precond)
+        return _lib.SolveOpts(tol=tol, restart=restart, max_iter=max_iter, use_precond=int(up))
+
+    def solve_workspace(self, nrhs: int, restart=20, use_precond=1) -> int:
+        """Device bytes the library allocates for one solve of nrhs columns (b, x and
+        this binding's transposed copies not included)."""
+        n = C.c_size_t(0)
+        opts = self._solve_opts(1e-4, restart, 1, use_precond)
+        check(lib().hodbf_solve_workspace(self._h, int(nrhs), C.byref(opts), C.byref(n)))
+        return n.value
+
     def solve(self, b: torch.Tensor, tol=1e-4, restart=20, max_iter=3000, use_precond=1):
         """x ~ Z^{-1} b by right-preconditioned FGMRES; returns (x, info dict).
 
@@ -129,9 +143,7 @@ class Operator:
             raise ValueError("b must be complex128")
         bc, R = _as_cols(b, self.n)
         x = torch.empty_like(bc)
-        up = {"fp32": 8 + P_FP32, "bf16": 8 + P_BF16, "fp16": 8 + P_FP16,
-              "fp32_split": 16 + P_FP32}.get(use_precond, use_precond)
-        opts = _lib.SolveOpts(tol=tol, restart=restart, max_iter=max_iter, use_precond=int(up))
+        opts = self._solve_opts(tol, restart, max_iter, use_precond)
         iters = np.zeros(R, dtype=np.int32)
         conv = np.zeros(R, dtype=np.int32)
         rel = np.zeros(R, dtype=np.float64)

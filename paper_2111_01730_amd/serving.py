@@ -72,9 +72,20 @@ def scatterer_key(grid) -> str:
 
 
 def solve_workspace_bytes(n: int, nrhs: int, restart: int) -> int:
-    """Device scratch of one vie_solve (Krylov basis, preconditioned basis, vectors)."""
-    per = (restart + 1) * 16 + restart * 8 + 4 * 16 + 2 * 8
+    """Estimate of one batch's device memory before its operator exists: the solve's
+    workspace (Krylov basis (restart + 1) x 16, preconditioned basis restart x 8, six
+    vectors, column staging, an apply workspace taken as 4 N rows) plus the right-hand
+    sides and solutions, bytes per unknown and column, and 64 MiB for the rest.  Once the
+    operator is built, ``batch_bytes`` asks the library for the exact figure."""
+    per = (restart + 1) * 16 + restart * 8 + 6 * 16 + 16 + 4 * 8 + 2 * 16
     return int(n) * int(nrhs) * per + (64 << 20)
+
+
+def batch_bytes(op, nrhs: int, restart: int, use_precond) -> int:
+    """Device memory of one batched solve on a built operator: the library's solve
+    workspace for these arguments plus the right-hand sides and the solutions (complex
+    FP64, N x nrhs each)."""
+    return int(op.solve_workspace(nrhs, restart, use_precond)) + 2 * 16 * int(op.n) * int(nrhs)
 
 
 class Server:
@@ -207,7 +218,7 @@ class Server:
                             if item[3] == key and cols + len(item[0].dirs) <= self.max_rhs:
                                 batch.append(item)
                                 cols += len(item[0].dirs)
-                        ws = solve_workspace_bytes(req0.grid.n, cols, self.restart)
+                        ws = batch_bytes(ent["op"], cols, self.restart, self.use_precond)
                         if ws > self.budget:
                             for item in batch:
                                 self._pending.remove(item)

@@ -171,6 +171,11 @@ def test_zero_rhs_and_errors(hod):
         op.solve(b, use_precond="fp32_split")
     with pytest.raises(HodbfError):  # no split form of the BF16 copy
         op.solve(b, use_precond=16 + hod.P_BF16)
+    with pytest.raises(HodbfError):  # workspace of a solve that would be refused
+        op.solve_workspace(4, use_precond="fp32_split")
+    with pytest.raises(HodbfError):
+        op.solve_workspace(4, restart=0, use_precond=0)
+    assert op.solve_workspace(4, use_precond=0) > 0
 
 
 def test_gmres_unpreconditioned_matches_lu(hod):
@@ -221,8 +226,19 @@ def test_allocator_hook_routes_memory_through_torch(ragged, hod):
         y = op.apply(x).cpu().numpy()
         assert np.all(_rel(y, y0) <= 1e-6)
         b = op.plane_wave(c["dirs"][:3])
+        ws = op.solve_workspace(3, restart=20, use_precond=1)
+        torch.cuda.synchronize()
+        base = torch.cuda.memory_allocated()
+        torch.cuda.reset_peak_memory_stats()
         xs, info = op.solve(b, tol=1e-6, use_precond=1)
+        torch.cuda.synchronize()
         assert info["converged"].all() and np.all(info["relres"] <= 1e-6)
+        # hodbf_solve_workspace reports the solve's own device memory: the peak beyond
+        # the solution tensor, up to the caching allocator's rounding
+        extra = torch.cuda.max_memory_allocated() - base - xs.numel() * 16
+        assert ws <= extra <= ws + (1 << 20), (ws, extra)
+        assert op.solve_workspace(6, restart=20, use_precond=1) > ws
+        assert op.solve_workspace(0) == 0
         op.close()
         torch.cuda.synchronize()
         assert torch.cuda.memory_allocated() - before <= held - st["bytes_fwd"]

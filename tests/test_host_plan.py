@@ -101,4 +101,5 @@ def test_null_arguments_rejected():
     assert L.hodbf_plan_probe(None, 0, None, C.byref(n)) == -1
     assert L.hodbf_stats(None, None) == -1
     assert L.hodbf_apply(None, 1, 0, None, 1, None, 1, None) == -1
+    assert L.hodbf_solve_workspace(None, 1, None, C.byref(n)) == -1
     L.hodbf_free(None)

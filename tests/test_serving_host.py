@@ -27,6 +27,9 @@ class FakeOp:
     def stats(self):
         return {"bytes_total": self.n * 1000}
 
+    def solve_workspace(self, nrhs, restart, use_precond):
+        return serving.solve_workspace_bytes(self.n, nrhs, restart) - 2 * 16 * self.n * nrhs
+
     def plane_wave(self, dirs):
         return torch.ones((self.n, len(dirs)), dtype=torch.complex128)
 
