@@ -42,11 +42,11 @@ PEAK_BF16_MFMA_TFLOPS = 2500.0
 # the rocSOLVER factorisations of the preconditioner's construction; the same kernel on
 # the forward operator (profiles/grouped_mfma_s3_forward_c2_r64_traffic.md) moves the
 # same bytes as the FP32 kernel, 1.16x its algorithmic bytes.
-MEASURED_TRAFFIC = {"sources_sha256": "7322aeba1294581260cd167acbc7a803d8f4938e930e3fefa28ce9ac6d904c9d",
+MEASURED_TRAFFIC = {"sources_sha256": "a4e5325f07b66f58abcad602c79278e2fe64e77e766a219287623a0ca889ffb2",
                     "precond_s3": {"bytes_per_apply": None, "launches_per_apply": 55},
-                    "forward_f32": {"bytes_per_apply": 1317051665.7 + 435898304.0,
+                    "forward_f32": {"bytes_per_apply": 1317203699.8 + 435897536.0,
                                     "launches_per_apply": 10},
-                    "forward_s3": {"bytes_per_apply": 1315968014.7 + 435858896.0,
+                    "forward_s3": {"bytes_per_apply": 1315848060.8 + 435860016.0,
                                    "launches_per_apply": 10}}
 
 
@@ -225,20 +225,26 @@ def apply_mode(args, cfg, Operator, P_NONE):
         dst.copy_(ref)
     torch.cuda.synchronize()
     reps = max(1, args.steps)
+    if args.user_order and which != 0:
+        raise SystemExit("--user-order applies the forward operator (which 0)")
+    # user order: the C ABI's hodbf_apply on complex FP64 columns (gather to tree order
+    # and FP32, the apply, scatter back to user order and FP64)
+    run = (lambda: op.apply(b)) if args.user_order else (lambda: op.apply_tree(xt, which))
     for _ in range(args.warmup):
-        op.apply_tree(xt, which)
+        run()
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(reps):
-        op.apply_tree(xt, which)
+        run()
     e1.record(stream)
     torch.cuda.synchronize()
     t = e0.elapsed_time(e1) / reps * 1e-3
     ent = st["entries_pre"] if pre else st["entries_fwd"]
     fl = 8.0 * R * ent
-    print(json.dumps({"mode": "apply", "which": which, "nrhs": R, "apply_ms": t * 1e3,
+    print(json.dumps({"mode": "apply", "which": which, "user_order": args.user_order,
+                      "nrhs": R, "apply_ms": t * 1e3,
                       "apply_gflops": fl / t / 1e9,
                       "launches_per_apply": st["pre_stages"] if pre else st["fwd_stages"],
                       "entries": ent, "io_rows": st["io_rows_pre"] if pre else st["io_rows_fwd"],
@@ -372,6 +378,9 @@ def main():
     ap.add_argument("--apply-reps", type=int, default=20)
     ap.add_argument("--apply-nrhs", type=int, default=0,
                     help="--mode apply: right-hand sides (0: the workload's 64)")
+    ap.add_argument("--user-order", action="store_true",
+                    help="--mode apply, which 0: hodbf_apply on the user's complex FP64 "
+                         "vectors (gather, apply, scatter) instead of the tree-order apply")
     ap.add_argument("--which", type=int, default=0,
                     help="--mode apply: 0 forward, 6 preconditioner on split-BF16 arithmetic")
     args = ap.parse_args()

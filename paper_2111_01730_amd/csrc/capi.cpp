@@ -164,6 +164,9 @@ void apply_precond_tree(const hodbf_op &op, int ftype, const float2 *x, float2 *
 static void upload_geometry(hodbf_op &op, hipStream_t st) {
   const Tree &t = op.tree;
   op.dev.perm.upload(t.perm.data(), t.perm.size() * sizeof(int32_t), st);
+  std::vector<int32_t> tpos(t.perm.size());
+  for (size_t i = 0; i < t.perm.size(); ++i) tpos[size_t(t.perm[i])] = int32_t(i);
+  op.dev.tpos.upload(tpos.data(), tpos.size() * sizeof(int32_t), st);
   std::vector<short4> xyz(static_cast<size_t>(t.n));
   for (int64_t i = 0; i < t.n; ++i) xyz[size_t(i)] = make_short4(t.cx[size_t(i)], t.cy[size_t(i)], t.cz[size_t(i)], 0);
   op.dev.xyz.upload(xyz.data(), xyz.size() * sizeof(short4), st);
@@ -319,7 +322,7 @@ hodbf_status hodbf_apply(const hodbf_op *op, int32_t nrhs, hodbf_dtype dtype, co
     float2 *yt = reinterpret_cast<float2 *>(buf + vbytes);
     float2 *wk = reinterpret_cast<float2 *>(buf + 2 * vbytes);
     const bool c128 = dtype == HODBF_C128;
-    launch_gather(x, c128, ldx, xt, false, op->dev.perm.as<int32_t>(), n, nrhs, st);
+    launch_gather(x, c128, ldx, xt, false, op->dev.tpos.as<int32_t>(), n, nrhs, st);
     apply_forward_tree(*op, xt, yt, wk, nrhs, st);
     launch_scatter(yt, false, y, c128, ldy, op->dev.perm.as<int32_t>(), n, nrhs, st);
     HIPCHK(hipGetLastError());
@@ -343,7 +346,7 @@ hodbf_status hodbf_precond_apply(const hodbf_op *op, int32_t nrhs, hodbf_dtype d
     float2 *zt = reinterpret_cast<float2 *>(buf + vbytes);
     float2 *wk = reinterpret_cast<float2 *>(buf + 2 * vbytes);
     const bool c128 = dtype == HODBF_C128;
-    launch_gather(x, c128, ldx, xt, false, op->dev.perm.as<int32_t>(), n, nrhs, st);
+    launch_gather(x, c128, ldx, xt, false, op->dev.tpos.as<int32_t>(), n, nrhs, st);
     apply_precond_tree(*op, op->pre.default_ft, xt, zt, wk, nrhs, st);
     launch_scatter(zt, false, y, c128, ldy, op->dev.perm.as<int32_t>(), n, nrhs, st);
     HIPCHK(hipGetLastError());
@@ -416,7 +419,7 @@ hodbf_status hodbf_stats(const hodbf_op *op, hodbf_stats_t *s) {
     s->bytes_fwd = int64_t(op->fwdF.bytes);
     s->bytes_pre = int64_t(op->pre.F32.bytes + op->pre.BF16.bytes + op->pre.F16.bytes);
     s->bytes_total = s->bytes_fwd + s->bytes_pre + int64_t(op->fwd.segs.bytes + op->fwd.pairs.bytes) +
-                     int64_t(op->dev.perm.bytes + op->dev.xyz.bytes + op->dev.inv_eps.bytes +
+                     int64_t(op->dev.perm.bytes + op->dev.tpos.bytes + op->dev.xyz.bytes + op->dev.inv_eps.bytes +
                              op->dev.kappa.bytes);
     s->fwd_stages = int32_t(op->fwd.launches.size());
     int ps = int(op->pre.leaf.launches.size());

@@ -61,8 +61,9 @@ void launch_entries(const EntryJob *jobs, int64_t njobs, const int32_t *cols, co
 // user-order column-major (ld) <-> tree-order RHS-interleaved, with dtype conversion.
 // src_c128 / dst_c128 select complex FP64 (true) or FP32 (false) on the user side;
 // the tree side is complex FP32 (tree_c128 = false) or FP64.
+// tpos[u] = tree position of user index u; perm[i] = user index at tree position i.
 void launch_gather(const void *src, bool src_c128, int64_t ld, void *dst, bool dst_c128,
-                   const int32_t *perm, int64_t n, int R, hipStream_t st);
+                   const int32_t *tpos, int64_t n, int R, hipStream_t st);
 void launch_scatter(const void *src, bool src_c128, void *dst, bool dst_c128, int64_t ld,
                     const int32_t *perm, int64_t n, int R, hipStream_t st);
 

@@ -126,7 +126,7 @@ static void solve_impl(const hodbf_op &op, int R, const void *b, int64_t ldb, vo
   gs.active = cv.take<int32_t>(R);
   if (cv.off > ws) fail(HODBF_E_HIP, "internal: solve buffers exceed the sized workspace");
 
-  const int32_t *perm = op.dev.perm.as<int32_t>();
+  const int32_t *tpos = op.dev.tpos.as<int32_t>(), *perm = op.dev.perm.as<int32_t>();
   auto norms2 = [&](const double2 *v, std::vector<double> &out) {
     launch_multidot(v, 0, 1, v, n, R, partial, nblk, st);
     launch_reduce_partials(partial, nblk, 1, R, sq, 0, st);
@@ -160,7 +160,7 @@ static void solve_impl(const hodbf_op &op, int R, const void *b, int64_t ldb, vo
       HIPCHK(hipMemcpyAsync(dst, tmp, size_t(rows * Rd) * sizeof(T), hipMemcpyDeviceToDevice, st));
   };
 
-  launch_gather(b, true, ldb, bt, true, perm, n, R, st);
+  launch_gather(b, true, ldb, bt, true, tpos, n, R, st);
   HIPCHK(hipMemsetAsync(xt, 0, NR * 16, st));
   std::vector<double> bn2, rn2;
   norms2(bt, bn2);

@@ -909,29 +909,37 @@ __device__ inline double2 cvt<float2, double2>(float2 v) {
   return make_double2(double(v.x), double(v.y));
 }
 
+// A workgroup takes 64 consecutive user indices u and 32 right-hand sides.  The user
+// side moves one column's 64 elements as one contiguous run per wave; the tree side
+// moves one element's 32 right-hand sides as one contiguous run at tree position
+// tpos[u].
 template <typename S, typename D>
 __global__ __launch_bounds__(256) void k_gather(const S *__restrict__ src, int64_t ld,
                                                 D *__restrict__ dst,
-                                                const int32_t *__restrict__ perm, int64_t n,
+                                                const int32_t *__restrict__ tpos, int64_t n,
                                                 int R) {
   __shared__ D tile[64][33];
-  const int64_t i0 = int64_t(blockIdx.x) * 64;
+  const int64_t u0 = int64_t(blockIdx.x) * 64;
   const int q0 = blockIdx.y * 32;
   for (int e = threadIdx.x; e < 64 * 32; e += 256) {
-    const int il = e & 63, ql = e >> 6;
-    const int64_t i = i0 + il;
+    const int ul = e & 63, ql = e >> 6;
+    const int64_t u = u0 + ul;
     const int q = q0 + ql;
-    if (i < n && q < R) tile[il][ql] = cvt<S, D>(src[int64_t(perm[i]) + int64_t(q) * ld]);
+    if (u < n && q < R) tile[ul][ql] = cvt<S, D>(src[u + int64_t(q) * ld]);
   }
   __syncthreads();
   for (int e = threadIdx.x; e < 64 * 32; e += 256) {
-    const int ql = e & 31, il = e >> 5;
-    const int64_t i = i0 + il;
+    const int ql = e & 31, ul = e >> 5;
+    const int64_t u = u0 + ul;
     const int q = q0 + ql;
-    if (i < n && q < R) dst[i * R + q] = tile[il][ql];
+    if (u < n && q < R) dst[int64_t(tpos[u]) * R + q] = tile[ul][ql];
   }
 }
 
+// The reverse direction keeps tree rows as the staged unit: a workgroup takes 64
+// consecutive tree positions and 32 right-hand sides, reads each position's 32 values as
+// one run and writes user index perm[i] of each column (measured faster than the
+// gather's arrangement for this direction).
 template <typename S, typename D>
 __global__ __launch_bounds__(256) void k_scatter(const S *__restrict__ src, D *__restrict__ dst,
                                                  int64_t ld, const int32_t *__restrict__ perm,
@@ -955,21 +963,21 @@ __global__ __launch_bounds__(256) void k_scatter(const S *__restrict__ src, D *_
 }
 
 void launch_gather(const void *src, bool src_c128, int64_t ld, void *dst, bool dst_c128,
-                   const int32_t *perm, int64_t n, int R, hipStream_t st) {
+                   const int32_t *tpos, int64_t n, int R, hipStream_t st) {
   if (n <= 0 || R <= 0) return;
   dim3 grid(unsigned((n + 63) / 64), unsigned((R + 31) / 32));
   if (src_c128 && dst_c128)
     hipLaunchKernelGGL((k_gather<double2, double2>), grid, dim3(256), 0, st,
-                       (const double2 *)src, ld, (double2 *)dst, perm, n, R);
+                       (const double2 *)src, ld, (double2 *)dst, tpos, n, R);
   else if (src_c128)
     hipLaunchKernelGGL((k_gather<double2, float2>), grid, dim3(256), 0, st,
-                       (const double2 *)src, ld, (float2 *)dst, perm, n, R);
+                       (const double2 *)src, ld, (float2 *)dst, tpos, n, R);
   else if (dst_c128)
     hipLaunchKernelGGL((k_gather<float2, double2>), grid, dim3(256), 0, st,
-                       (const float2 *)src, ld, (double2 *)dst, perm, n, R);
+                       (const float2 *)src, ld, (double2 *)dst, tpos, n, R);
   else
     hipLaunchKernelGGL((k_gather<float2, float2>), grid, dim3(256), 0, st, (const float2 *)src,
-                       ld, (float2 *)dst, perm, n, R);
+                       ld, (float2 *)dst, tpos, n, R);
 }
 
 void launch_scatter(const void *src, bool src_c128, void *dst, bool dst_c128, int64_t ld,

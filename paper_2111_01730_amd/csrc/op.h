@@ -97,7 +97,8 @@ struct PrecondData {
 };
 
 struct OpDevice {
-  DevBuf perm;      // int32, tree position -> user index
+  DevBuf perm;      // int32, tree position -> user index (scatter)
+  DevBuf tpos;      // int32, user index -> tree position (gather)
   DevBuf xyz;       // short4 voxel coordinates, tree order
   DevBuf inv_eps;   // double2, tree order
   DevBuf kappa;     // double2, tree order
