@@ -555,13 +555,18 @@ typedef float floatx2v __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 // LDS planes of the split-BF16 kernel (32-bit words): hi and lo parts apart, so that a
 // fragment is one 16-byte read straight into the MFMA operand registers.  A plane holds
-// 64 rows (factor) or 64 right-hand-side columns (input) of kS3 words, K = 0..15 packed
-// (re | im << 16) in words 0..15 of each.  A stride of 20 words puts 16 consecutive rows
-// of one 4-word K group on distinct banks; the second input form sits 32 words further
-// modulo 64, so the 16 lanes of an input fragment read (8 columns x both forms) do too.
-constexpr int kS3 = kKC + 4;
-constexpr int kPlane = 64 * kS3;     // words of one plane
-constexpr int kXF = 2 * kPlane + 32;  // words between the two input forms (hi + lo planes each)
+// 64 rows (factor) or 64 right-hand-side columns (input) of K = 0..15, packed
+// (re | im << 16), in 16-byte units of four K values, K-group-major: the unit of row r
+// and K group kk sits at unit kk * 64 + r.  gfx950 serves a 16-byte LDS read in four
+// groups of 16 lanes, each holding every value of lane mod 16 once (lanes 0-3, 12-15,
+// 20-23, 24-27; 4-7, 8-11, 16-19, 28-31; and the same pattern plus 32); a fragment's
+// lane 16 kk + i16 reads row i16 of its row tile, so unit kk * 64 + r puts the 16 lanes of
+// every group on distinct banks, and the staging stores of a wave (64 consecutive rows,
+// one K group) are one contiguous kilobyte.  The second input form sits 8 units further
+// modulo 16, so an input fragment's 8 columns x both forms cover distinct banks too.
+constexpr int kS3Unit = 4;                 // words per unit
+constexpr int kPlane = 4 * 64 * kS3Unit;   // words of one plane (4 K groups x 64 rows)
+constexpr int kXF = 2 * kPlane + 32;       // words between the two input forms (hi + lo planes each)
 
 // Chunk loads of the split-BF16 kernel: thread (lane l, wave g) fetches factor row l and
 // input column l at K rows kb + 4 g .. kb + 4 g + 3, so that it can write its four values
@@ -614,8 +619,8 @@ __device__ __forceinline__ void tile_item_s3(const int it, const int nsl, const 
   const int qo = i16 >> 1, op = i16 & 1;
   // this lane's fragment bases (hi planes; lo at + kPlane): factor row wr * 16 + i16, input
   // column wc * 8 + qo of form op, K group kk
-  const uint32_t *al = as + (wr * 16 + i16) * kS3 + 4 * kk;
-  const uint32_t *xl = xs + op * kXF + (wc * 8 + qo) * kS3 + 4 * kk;
+  const uint32_t *al = as + (kk * 64 + wr * 16 + i16) * kS3Unit;
+  const uint32_t *xl = xs + op * kXF + (kk * 64 + wc * 8 + qo) * kS3Unit;
   const Seg sg = segs[it / nsl];
   const int q0 = (it % nsl) * RQ;
   const int Rc = min(R - q0, RQ);
@@ -659,7 +664,7 @@ __device__ __forceinline__ void tile_item_s3(const int it, const int nsl, const 
       h[j] = split_bf16(okx ? xr[j].x : 0.f, okx ? xr[j].y : 0.f);
       a[j] = split_bf16(oka ? ar[j].x * c.scale : 0.f, oka ? ar[j].y * c.scale : 0.f);
     }
-    const int o = l * kS3 + 4 * g;
+    const int o = (g * 64 + l) * kS3Unit;
     constexpr uint32_t sg = 0x80000000u;
     auto rot = [](uint32_t v) { return __builtin_amdgcn_alignbit(v, v, 16); };
     *reinterpret_cast<u32x4 *>(as + o) = u32x4{a[0].x, a[1].x, a[2].x, a[3].x};
@@ -677,7 +682,7 @@ __device__ __forceinline__ void tile_item_s3(const int it, const int nsl, const 
       bf16x8 xh[NCI], xo[NCI];
 #pragma unroll
       for (int ci = 0; ci < NCI; ++ci) {
-        const uint32_t *b = xl + ci * CW * 8 * kS3;
+        const uint32_t *b = xl + ci * CW * 8 * kS3Unit;
         xh[ci] = *reinterpret_cast<const bf16x8 *>(b);
         xo[ci] = *reinterpret_cast<const bf16x8 *>(b + kPlane);
       }
@@ -685,7 +690,7 @@ __device__ __forceinline__ void tile_item_s3(const int it, const int nsl, const 
       // three products run term-major, so consecutive MFMAs alternate accumulators
 #pragma unroll
       for (int ri = 0; ri < NRI; ++ri) {
-        const uint32_t *a = al + ri * RW * 16 * kS3;
+        const uint32_t *a = al + ri * RW * 16 * kS3Unit;
         const bf16x8 ah = *reinterpret_cast<const bf16x8 *>(a);
         const bf16x8 ao = *reinterpret_cast<const bf16x8 *>(a + kPlane);
 #pragma unroll
