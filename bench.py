@@ -42,11 +42,11 @@ PEAK_BF16_MFMA_TFLOPS = 2500.0
 # the rocSOLVER factorisations of the preconditioner's construction; the same kernel on
 # the forward operator (profiles/grouped_mfma_s3_forward_c2_r64_traffic.md) moves the
 # same bytes as the FP32 kernel, 1.16x its algorithmic bytes.
-MEASURED_TRAFFIC = {"sources_sha256": "761f6695d7fdd75cc3312a143e627037b913afd61314dab33125257c973fa2a1",
+MEASURED_TRAFFIC = {"sources_sha256": "d6d7a7c7dc25f3fb8c1f9f370d59ee165a714aaad5cb670eed530a3e9aeb1bc3",
                     "precond_s3": {"bytes_per_apply": None, "launches_per_apply": 55},
-                    "forward_f32": {"bytes_per_apply": 1317099070.6 + 435898704.0,
+                    "forward_f32": {"bytes_per_apply": 1317107336.2 + 435898768.0,
                                     "launches_per_apply": 10},
-                    "forward_s3": {"bytes_per_apply": 1315828775.9 + 435858864.0,
+                    "forward_s3": {"bytes_per_apply": 1316882448.0 + 435870976.0,
                                    "launches_per_apply": 10}}
 
 

@@ -729,9 +729,10 @@ __device__ __forceinline__ void tile_item_s3(const int it, const int nsl, const 
   store_item<NRI, NCI, RW>(sg, rowmap, OUT, R, beta, q0, Rc, wr, wc, acc);
 }
 
-// Five waves per SIMD (96 VGPRs; the register allocator spills one value to scratch):
-// measured faster than four at 1-16 right-hand sides and equal at 64.
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_grouped_mfma_s3(
+// Six waves per SIMD (80 VGPRs, no spills; six workgroups' 24.7 KB of LDS fit a CU's
+// 160 KB): 1-2% faster than five at 1-64 right-hand sides, and five faster than four at
+// 1-16.
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_grouped_mfma_s3(
     const Seg *__restrict__ segs, const Pair *__restrict__ pairs, const RowMap *__restrict__ rowmap,
     const float2 *__restrict__ F, const float2 *__restrict__ X, const float2 *__restrict__ T,
     float2 *__restrict__ OUT, int R, int beta, int RQ, int nsl, TileClasses tc) {
