@@ -252,6 +252,30 @@ def apply_mode(args, cfg, Operator, P_NONE):
     return 0
 
 
+def solves_mode(args, cfg, Operator):
+    """Only the batched mixed solves of the main measurement (the profiled command for the
+    solve's kernel breakdown): --warmup untimed solves, then --steps timed ones."""
+    import torch
+
+    from paper_2111_01730_amd.hodbf import P_FP32
+    op = Operator(cfg["grid"], tol_con=cfg["tol"], tol_fact=args.tol_fact, precond=P_FP32,
+                  seed=cfg["seed"], precond_dense_levels=args.precond_dense_levels)
+    b = op.plane_wave(cfg["dirs"])
+    for _ in range(args.warmup):
+        op.solve(b, tol=TOL_SOL, use_precond="fp32_split")
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for _ in range(max(1, args.steps)):
+        _, info = op.solve(b, tol=TOL_SOL, use_precond="fp32_split")
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - ts) / max(1, args.steps)
+    print(json.dumps({"mode": "solves", "ms_per_solve": t * 1e3, "nrhs": int(b.shape[1]),
+                      "iters_max": int(info["iters"].max()),
+                      "iters_mean": float(info["iters"].mean()),
+                      "converged": bool(info["converged"].all())}), flush=True)
+    return 0
+
+
 def serve_mode(args):
     """Poisson stream of solve requests through the continuous-batching server."""
     from paper_2111_01730_amd import serving
@@ -358,7 +382,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--tol-fact", type=float, default=1e-4)
-    ap.add_argument("--mode", choices=["solve", "apply", "serve", "config", "oracle"],
+    ap.add_argument("--mode", choices=["solve", "solves", "apply", "serve", "config", "oracle"],
                     default="solve")
     ap.add_argument("--config", default="c3_sphere_64", help="workload of --mode config")
     ap.add_argument("--precond-min-level", type=int, default=0)
@@ -407,6 +431,8 @@ def main():
     R = cfg["nrhs"]
     if args.mode == "apply":
         return apply_mode(args, cfg, Operator, P_NONE)
+    if args.mode == "solves":
+        return solves_mode(args, cfg, Operator)
     if args.mode == "serve":
         return serve_mode(args)
     if args.mode == "config":
