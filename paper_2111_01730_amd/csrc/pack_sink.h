@@ -28,7 +28,9 @@ void pack_group(PackSink &pk, const Tree &t, const std::vector<const Butterfly *
                 const std::function<void(const Butterfly &, int64_t *)> &meta);
 void upload_program(Program &prog, PackSink &pk, hipStream_t st);
 // Launches with fewer tiles than this get half-height tiles at upload (more workgroups).
-constexpr int64_t kRetileBelow = 1024;
+// 512: with six waves per SIMD the split-BF16 kernel is 5-9% faster than with 1024 at
+// 1-64 right-hand sides (the FP32 kernel is indifferent), and no faster with 0-384.
+constexpr int64_t kRetileBelow = 512;
 // Re-emit every launch's tiles, cutting those of launches with fewer than `below` tiles
 // into tiles of at most `rows` rows (pairs offset to the rows, row maps clipped).
 void retile(PackSink &pk, int64_t below, int rows);
