@@ -42,7 +42,7 @@ PEAK_BF16_MFMA_TFLOPS = 2500.0
 # the rocSOLVER factorisations of the preconditioner's construction; the same kernel on
 # the forward operator (profiles/grouped_mfma_s3_forward_c2_r64_traffic.md) moves the
 # same bytes as the FP32 kernel, 1.16x its algorithmic bytes.
-MEASURED_TRAFFIC = {"sources_sha256": "c552b604491f18697ba141e01d1cd18e36b0ed9da15e79ccb704065678530757",
+MEASURED_TRAFFIC = {"sources_sha256": "fd800eacd5218873512ff346d077dc865ebbbedcbe1ea35c9cc968d21953c03d",
                     "precond_s3": {"bytes_per_apply": None, "launches_per_apply": 55},
                     "forward_f32": {"bytes_per_apply": 1309388425.0 + 435899936.0,
                                     "launches_per_apply": 10},

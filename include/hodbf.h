@@ -133,8 +133,8 @@ hodbf_status hodbf_precond_apply(const hodbf_op *op, int32_t nrhs, hodbf_dtype d
  * 2 with the FP32 copy; 3 with the BF16 copy; 4 with the FP16 copy; 5 y = Z_con x and
  * 6 y = P x (FP32 copy), both with split-BF16 arithmetic: every FP32 factor and input
  * value is split into BF16 hi + lo parts and each product is hi hi + hi lo + lo hi on
- * BF16 MFMA with FP32 accumulation (relative error about 2^-17 per product, against
- * 2^-24 for 0 and 2).  Only grouped-GEMM kernels run (no permutation), so callers that
+ * BF16 MFMA with FP32 accumulation (relative error at most 2^-15 per product, about
+ * 2^-18 typically, against 2^-24 for 0 and 2).  Only grouped-GEMM kernels run (no permutation), so callers that
  * keep data in tree order avoid two passes.
  * x and y must not overlap.  E_STATE if the requested factors are absent.
  */

@@ -536,9 +536,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
 
 // Split-BF16 arithmetic for complex FP32 factors and inputs.  Each FP32 value v is
 // written as hi + lo with hi = bf16(v) and lo = bf16(v - hi), both rounded to nearest
-// even, so |v - hi - lo| <= 2^-18 |v|; a product a x is taken as
-// hi_a hi_x + hi_a lo_x + lo_a hi_x (the dropped lo_a lo_x is below 2^-18 |a x|) on
-// v_mfma_f32_16x16x32_bf16 with FP32 accumulation.  One MFMA consumes a whole chunk of
+// even, so |v - hi - lo| <= 2^-17 |v|; a product a x is taken as
+// hi_a hi_x + hi_a lo_x + lo_a hi_x on v_mfma_f32_16x16x32_bf16 with FP32 accumulation:
+// the dropped lo_a lo_x (at most 2^-16 |a x|) and the two split remainders (2^-17 each)
+// keep it within 2^-15 |a| |x|.  One MFMA consumes a whole chunk of
 // 16 complex columns (32 real K), against eight FP32 16x16x4 MFMAs of four times the
 // cycles each: the same tiles, work items and chunk pipeline as tile_item, with the
 // chunk split into hi / lo once, when it is written to LDS.

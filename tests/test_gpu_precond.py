@@ -42,10 +42,10 @@ def case():
     return c, g, op, vie.dense(g)
 
 
-# which 6: the FP32 copy with split-BF16 arithmetic, 2^-17-class rounding per product
-# against FP32's 2^-24, i.e. 128 x the FP32 tolerance
+# which 6: the FP32 copy with split-BF16 arithmetic, at most 2^-15 of |a| |x| per product
+# against FP32's 2^-24, i.e. 512 x the FP32 tolerance
 @pytest.mark.parametrize("copy,which,tol", [("fp32", 2, 2e-5), ("fp16", 4, 2e-5), ("bf16", 3, 2e-2),
-                                            ("fp32", 6, 128 * 2e-5)])
+                                            ("fp32", 6, 512 * 2e-5)])
 @pytest.mark.parametrize("R", [1, 8])
 def test_precond_apply_matches_exported_factors(case, copy, which, tol, R):
     # the oracle re-applies the GPU's stored factors (values as stored, block scales
