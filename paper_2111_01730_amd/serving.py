@@ -126,6 +126,11 @@ class Server:
     # ------------------------------------------------------------------ public
     def submit(self, req: Request) -> Future:
         fut: Future = Future()
+        if not 1 <= len(req.dirs) <= self.max_rhs:
+            # a request wider than one batch could never be admitted
+            fut.set_exception(ValueError(
+                f"request {req.id}: {len(req.dirs)} right-hand sides, 1..{self.max_rhs} allowed"))
+            return fut
         key = scatterer_key(req.grid)
         with self._lock:
             self._pending.append((req, fut, time.perf_counter(), key))
@@ -218,7 +223,14 @@ class Server:
                             if item[3] == key and cols + len(item[0].dirs) <= self.max_rhs:
                                 batch.append(item)
                                 cols += len(item[0].dirs)
-                        ws = batch_bytes(ent["op"], cols, self.restart, self.use_precond)
+                        try:
+                            ws = batch_bytes(ent["op"], cols, self.restart, self.use_precond)
+                        except Exception as e:  # e.g. a preconditioner copy the operator lacks
+                            for item in batch:
+                                self._pending.remove(item)
+                                item[1].set_exception(e)
+                            acted = True
+                            break
                         if ws > self.budget:
                             for item in batch:
                                 self._pending.remove(item)

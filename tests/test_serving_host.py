@@ -100,6 +100,35 @@ def test_request_that_cannot_fit_fails():
     srv.close()
 
 
+class NoWorkspaceOp(FakeOp):
+    """Stand-in whose library call for the solve's workspace fails (as for a
+    preconditioner copy the operator lacks)."""
+
+    def solve_workspace(self, nrhs, restart, use_precond):
+        raise RuntimeError("no such preconditioner copy")
+
+
+def test_failing_workspace_query_fails_the_batch_not_the_scheduler():
+    g = _grid(4)
+    srv = serving.Server(hbm_budget=1 << 40, slots=1, operator_factory=NoWorkspaceOp,
+                         est_bytes_per_unknown=1000)
+    with pytest.raises(RuntimeError):
+        srv.submit(_req(0, g)).result(timeout=10)
+    # the scheduler is still alive and serves the next request the same way
+    with pytest.raises(RuntimeError):
+        srv.submit(_req(1, g)).result(timeout=10)
+    srv.close()
+
+
+def test_request_wider_than_a_batch_is_refused():
+    g = _grid(5)
+    srv = serving.Server(hbm_budget=1 << 40, slots=1, max_rhs=4, operator_factory=FakeOp)
+    with pytest.raises(ValueError):
+        srv.submit(_req(0, g, r=5)).result(timeout=10)
+    assert srv.submit(_req(1, g, r=4)).result(timeout=10).converged
+    srv.close()
+
+
 def test_summary_percentiles():
     res = [serving.Result(i, np.zeros((1, 1)), np.ones(1), np.zeros(1), True, 0.0, 0.0, float(i + 1),
                           1, 1, False) for i in range(100)]
