@@ -176,80 +176,97 @@ class Server:
     def _estimate_op_bytes(self, grid) -> int:
         return int(self.est_per_unknown * grid.n)
 
-    def _try_evict(self, need: int) -> bool:
-        """Drop idle resident operators, least recently used first, until need fits."""
+    def _try_evict(self, need: int, keep=None) -> bool:
+        """Drop idle resident operators, least recently used first, until need fits.
+        The operator under ``keep`` (the one a batch is about to use) is never dropped."""
         while self.resident_bytes() + self._reserved + need > self.budget:
-            idle = [k for k, e in self._ops.items() if e["op"] is not None and e["busy"] == 0]
+            idle = [k for k, e in self._ops.items()
+                    if e["op"] is not None and e["busy"] == 0 and k != keep]
             if not idle:
                 return False
             self._ops.pop(idle[0])["op"].close()
         return True
+
+    def _fail_pending(self, exc: BaseException):
+        for item in list(self._pending):
+            self._pending.remove(item)
+            if not item[1].done():
+                item[1].set_exception(exc)
 
     def _loop(self):
         with self._lock:
             while True:
                 if self._closed and not self._pending and self._running == 0 and self._building == 0:
                     return
-                acted = False
-                # 1. start builds for pending scatterers that are neither resident nor
-                #    being built (own pool: builds never hold a solve slot)
-                if self._building < self.build_slots:
-                    for req0, _, _, key in self._pending:
-                        if key in self._ops:
-                            continue
-                        need = self._estimate_op_bytes(req0.grid)
-                        if need + solve_workspace_bytes(req0.grid.n, 1, self.restart) > self.budget:
-                            for item in [it for it in self._pending if it[3] == key]:
-                                self._pending.remove(item)
-                                item[1].set_exception(MemoryError(
-                                    f"operator needs about {need} bytes, budget {self.budget}"))
-                            acted = True
-                            break
-                        if self._try_evict(need):
-                            self._ops[key] = {"op": None, "bytes": need, "busy": 0}
-                            self._building += 1
-                            self._builder.submit(self._build, key, req0.grid)
-                            acted = True
-                        break  # oldest first; wait for memory otherwise
-                # 2. solve: the oldest request whose operator is resident leads a batch of
-                #    every pending request for that scatterer, up to max_rhs columns
-                if self._free_streams:
-                    for req0, _, _, key in self._pending:
-                        ent = self._ops.get(key)
-                        if ent is None or ent["op"] is None:
-                            continue
-                        batch, cols = [], 0
-                        for item in self._pending:
-                            if item[3] == key and cols + len(item[0].dirs) <= self.max_rhs:
-                                batch.append(item)
-                                cols += len(item[0].dirs)
-                        try:
-                            ws = batch_bytes(ent["op"], cols, self.restart, self.use_precond)
-                        except Exception as e:  # e.g. a preconditioner copy the operator lacks
-                            for item in batch:
-                                self._pending.remove(item)
-                                item[1].set_exception(e)
-                            acted = True
-                            break
-                        if ws > self.budget:
-                            for item in batch:
-                                self._pending.remove(item)
-                                item[1].set_exception(MemoryError(
-                                    f"solve needs {ws} bytes, budget {self.budget}"))
-                            acted = True
-                        elif self._try_evict(ws):
-                            for item in batch:
-                                self._pending.remove(item)
-                            self._reserved += ws
-                            self._running += 1
-                            ent["busy"] += 1
-                            self._ops.move_to_end(key)
-                            sidx = self._free_streams.pop()
-                            self._pool.submit(self._run_batch, key, batch, ws, sidx)
-                            acted = True
-                        break
+                try:
+                    acted = self._tick()
+                except Exception as e:  # a scheduler bug must not strand the waiting requests
+                    self._fail_pending(e)
+                    acted = True
                 if not acted:
                     self._lock.wait(timeout=0.05)
+
+    def _tick(self) -> bool:
+        """One pass of the scheduler under the lock; True if it changed anything."""
+        acted = False
+        # 1. start builds for pending scatterers that are neither resident nor
+        #    being built (own pool: builds never hold a solve slot)
+        if self._building < self.build_slots:
+            for req0, _, _, key in self._pending:
+                if key in self._ops:
+                    continue
+                need = self._estimate_op_bytes(req0.grid)
+                if need + solve_workspace_bytes(req0.grid.n, 1, self.restart) > self.budget:
+                    for item in [it for it in self._pending if it[3] == key]:
+                        self._pending.remove(item)
+                        item[1].set_exception(MemoryError(
+                            f"operator needs about {need} bytes, budget {self.budget}"))
+                    acted = True
+                    break
+                if self._try_evict(need):
+                    self._ops[key] = {"op": None, "bytes": need, "busy": 0}
+                    self._building += 1
+                    self._builder.submit(self._build, key, req0.grid)
+                    acted = True
+                break  # oldest first; wait for memory otherwise
+        # 2. solve: the oldest request whose operator is resident leads a batch of
+        #    every pending request for that scatterer, up to max_rhs columns
+        if self._free_streams:
+            for req0, _, _, key in self._pending:
+                ent = self._ops.get(key)
+                if ent is None or ent["op"] is None:
+                    continue
+                batch, cols = [], 0
+                for item in self._pending:
+                    if item[3] == key and cols + len(item[0].dirs) <= self.max_rhs:
+                        batch.append(item)
+                        cols += len(item[0].dirs)
+                try:
+                    ws = batch_bytes(ent["op"], cols, self.restart, self.use_precond)
+                except Exception as e:  # e.g. a preconditioner copy the operator lacks
+                    for item in batch:
+                        self._pending.remove(item)
+                        item[1].set_exception(e)
+                    acted = True
+                    break
+                if ws > self.budget:
+                    for item in batch:
+                        self._pending.remove(item)
+                        item[1].set_exception(MemoryError(
+                            f"solve needs {ws} bytes, budget {self.budget}"))
+                    acted = True
+                elif self._try_evict(ws, keep=key):
+                    for item in batch:
+                        self._pending.remove(item)
+                    self._reserved += ws
+                    self._running += 1
+                    ent["busy"] += 1
+                    self._ops.move_to_end(key)
+                    sidx = self._free_streams.pop()
+                    self._pool.submit(self._run_batch, key, batch, ws, sidx)
+                    acted = True
+                break
+        return acted
 
     # ------------------------------------------------------------------ workers
     def _build(self, key, grid):

@@ -135,3 +135,43 @@ def test_summary_percentiles():
     s = serving.summarize(res, 10.0)
     assert s["rhs"] == 100 and s["solves_per_s"] == 10.0
     assert abs(s["p50_latency_s"] - 50.5) < 1e-9 and s["p99_latency_s"] > 98
+
+
+def test_eviction_keeps_the_operator_the_batch_will_use():
+    """Two resident idle operators fill the budget but for a one-column workspace; a
+    two-column request for the least recently used one needs room, which must come from
+    evicting the other operator, never the one the batch is about to run on."""
+    g1, g2 = _grid(11), _grid(12)
+    n = g1.n
+    ws1 = serving.solve_workspace_bytes(n, 1, 20)
+    srv = serving.Server(hbm_budget=2 * n * 1000 + ws1, slots=1, operator_factory=FakeOp,
+                         est_bytes_per_unknown=1000)
+    srv.preload([g1, g2])  # g1 is now the least recently used resident operator
+    assert FakeOp.builds == 2 and FakeOp.closes == 0
+    res = srv.submit(_req(0, g1, r=2)).result(timeout=10)
+    assert res.converged and res.x.shape == (n, 2)
+    assert FakeOp.closes == 1 and FakeOp.builds == 2  # g2 went; g1 served without a rebuild
+    assert srv._sched.is_alive()
+    srv.close()
+
+
+def test_scheduler_error_fails_pending_requests():
+    """An exception inside one scheduler pass fails the requests that were waiting
+    instead of stranding them (and the scheduler keeps running)."""
+    g = _grid(13)
+    srv = serving.Server(hbm_budget=1 << 40, slots=1, operator_factory=FakeOp,
+                         est_bytes_per_unknown=1000)
+    calls = {"n": 0}
+    orig = srv._estimate_op_bytes
+
+    def broken(grid):
+        calls["n"] += 1
+        if calls["n"] == 1:
+            raise KeyError("planted scheduler fault")
+        return orig(grid)
+
+    srv._estimate_op_bytes = broken
+    with pytest.raises(KeyError):
+        srv.submit(_req(0, g)).result(timeout=10)
+    assert srv.submit(_req(1, g)).result(timeout=10).converged
+    srv.close()
