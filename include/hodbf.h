@@ -118,8 +118,9 @@ hodbf_status hodbf_apply(const hodbf_op *op, int32_t nrhs, hodbf_dtype dtype,
 /*
  * hodbf_precond_apply -- y = P x with P ~ Z^{-1}: the leaf inverses D_tau^{-1}
  * followed, level by level towards the root, by z(tau) <- (I + X_tau) z(tau)
- * (Algorithm 1 unrolled).  Uses the default copy: FP16 if stored, else FP32, else
- * BF16.  FP32 accumulation.  E_STATE if built without one.
+ * (Algorithm 1 unrolled).  Uses the default arithmetic: the FP32 copy with split-BF16
+ * products (see hodbf_apply_tree, which 6) if the FP32 copy is stored, else the FP16
+ * copy, else the BF16 copy.  FP32 accumulation.  E_STATE if built without one.
  */
 hodbf_status hodbf_precond_apply(const hodbf_op *op, int32_t nrhs, hodbf_dtype dtype,
                                  const void *x, int64_t ldx, void *y, int64_t ldy,
@@ -129,7 +130,7 @@ hodbf_status hodbf_precond_apply(const hodbf_op *op, int32_t nrhs, hodbf_dtype d
  * hodbf_apply_tree -- the same products on vectors already in the library's internal
  * layout: complex FP32, tree order (position t holds user index perm[t], see
  * hodbf_export selector 0), right-hand sides interleaved, element (t, q) at
- * ptr[t * nrhs + q].  which: 0 y = Z_con x; 1 y = P x with the default copy;
+ * ptr[t * nrhs + q].  which: 0 y = Z_con x; 1 y = P x with the default arithmetic;
  * 2 with the FP32 copy; 3 with the BF16 copy; 4 with the FP16 copy; 5 y = Z_con x and
  * 6 y = P x (FP32 copy), both with split-BF16 arithmetic: every FP32 factor and input
  * value is split into BF16 hi + lo parts and each product is hi hi + hi lo + lo hi on

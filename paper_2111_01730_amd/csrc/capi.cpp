@@ -22,11 +22,10 @@ void set_last_error(const std::string &msg) { g_last_error = msg; }
 [[noreturn]] void fail(hodbf_status code, const std::string &msg) { throw Error{code, msg}; }
 
 void logf(const char *fmt, ...) {
-  static const bool on = [] {
-    const char *e = std::getenv("HODBF_LOG");
-    return e && *e && std::strcmp(e, "0") != 0;
-  }();
-  if (!on) return;
+  // read at every message (cheap next to what is logged) so a caller can switch it on
+  // for one long call
+  const char *e = std::getenv("HODBF_LOG");
+  if (!(e && *e && std::strcmp(e, "0") != 0)) return;
   va_list ap;
   va_start(ap, fmt);
   std::fprintf(stderr, "[hodbf] ");

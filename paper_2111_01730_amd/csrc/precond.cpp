@@ -398,7 +398,9 @@ void build_precond(hodbf_op &op, hipStream_t st) {
   for (auto &r : pd.table) ent += r.m * r.n;
   pd.entries = ent;
   pd.max_rank = maxr;
-  pd.default_ft = wanth16 ? FT_F16 : (want32 ? FT_C64 : FT_BF16);
+  // default arithmetic: the FP32 copy on split-BF16 MFMA when it is stored (it
+  // preconditions like FP32 arithmetic at a lower cost), else FP16, else BF16
+  pd.default_ft = want32 ? FT_C64_S3 : (wanth16 ? FT_F16 : FT_BF16);
   pd.present = true;
   op.id_count += ids;
   pd.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

@@ -25,3 +25,22 @@ def pytest_collection_modifyitems(config, items):
     for it in items:
         if "gpu" in it.keywords:
             it.add_marker(skip)
+
+
+@pytest.fixture
+def live(request):
+    """Context manager that lets a long test's progress lines (and the library's own
+    HODBF_LOG messages on stderr) reach the terminal while pytest captures output."""
+    import contextlib
+
+    capman = request.config.pluginmanager.getplugin("capturemanager")
+
+    @contextlib.contextmanager
+    def ctx():
+        if capman is None:
+            yield
+            return
+        with capman.global_and_fixture_disabled():
+            yield
+
+    return ctx

@@ -12,12 +12,17 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def _check(name, fft_cols):
+def _check(name, fft_cols, live):
     from paper_2111_01730_amd.hodbf import Operator
     cfg = config(name)
     g = cfg["grid"]
-    print(f"[{name}: build N={g.n}]", flush=True)
-    op = Operator(g, tol_con=cfg["tol"], seed=cfg["seed"])
+    with live():  # the construction logs its progress (HODBF_LOG) past pytest's capture
+        print(f"[{name}: build N={g.n}]", flush=True)
+        os.environ["HODBF_LOG"] = "1"
+        try:
+            op = Operator(g, tol_con=cfg["tol"], seed=cfg["seed"])
+        finally:
+            os.environ.pop("HODBF_LOG", None)
     st = op.stats()
     print(f"[{name}: built in {st['build_seconds']:.1f} s, {st['entries_fwd']} entries, "
           f"max rank {st['max_rank']}]", flush=True)
@@ -35,8 +40,12 @@ def _check(name, fft_cols):
     y = y.cpu().numpy()
     bn = b.cpu().numpy()
     rows = cfg["rows"]
-    print(f"[{name}: direct sums on {len(rows)} rows]", flush=True)
-    ye = vie.direct_rows(g, bn, rows)
+    ye = np.empty((len(rows), bn.shape[1]), dtype=np.complex128)
+    with live():
+        for c0 in range(0, len(rows), 64):
+            ye[c0:c0 + 64] = vie.direct_rows(g, bn, rows[c0:c0 + 64])
+            print(f"[{name}: direct sums, {min(c0 + 64, len(rows))} of {len(rows)} rows]",
+                  flush=True)
     err = np.linalg.norm(y[rows] - ye, axis=0) / np.linalg.norm(ye, axis=0)
     assert np.all(err <= 10 * cfg["tol"]), err
     for q in fft_cols:
@@ -46,15 +55,15 @@ def _check(name, fft_cols):
     return st
 
 
-def test_c3_sphere_64_forward_apply_full_size():
-    st = _check("c3_sphere_64", fft_cols=[0, 31])
+def test_c3_sphere_64_forward_apply_full_size(live):
+    st = _check("c3_sphere_64", fft_cols=[0, 31], live=live)
     assert st["n"] == 64**3 and st["levels"] == 12
 
 
-@pytest.mark.skipif(os.environ.get("HODBF_LARGE_TESTS") != "1",
-                    reason="2.1M-unknown build takes many minutes; set HODBF_LARGE_TESTS=1")
-def test_c5_slabs_128_forward_apply_full_size():
-    st = _check("c5_slabs_128", fft_cols=[0])
+def test_c5_slabs_128_forward_apply_full_size(live):
+    """2.1M unknowns, 16 plane waves, chi_con = 1e-3: 512 rows by direct summation and
+    one whole column by the FFT-exact product, each within 10 chi_con."""
+    st = _check("c5_slabs_128", fft_cols=[0], live=live)
     assert st["n"] == 128**3 and st["levels"] == 15
 
 
@@ -104,67 +113,3 @@ def test_c5_slabs_128_preconditioned_solve():
     rel = np.linalg.norm(r) / np.linalg.norm(bn)
     print(f"[c5 solve: column 0 true residual with the exact product {rel:.3e}]", flush=True)
     assert rel <= tol + 10 * tol, rel
-
-
-def _norm2_estimate(g, its=15, seed=0):
-    """||Z||_2 from below by power iteration on Z^H Z with the oracle's FFT-exact product
-    (Z^H y = y / conj(eps) - conj(kappa) * conj(K conj(y)); K u is the convolution part
-    of the product, recovered from it with u / kappa as input)."""
-    kap = vie.contrast(g.eps)
-
-    def conv(u):
-        w = u / kap
-        return w / g.eps - vie.fft_matvec(g, w)
-
-    rng = np.random.default_rng(seed)
-    v = rng.standard_normal(g.n) + 1j * rng.standard_normal(g.n)
-    v /= np.linalg.norm(v)
-    s = 0.0
-    for _ in range(its):
-        zv = vie.fft_matvec(g, v)
-        s = np.linalg.norm(zv)
-        w = zv / np.conj(g.eps) - np.conj(kap) * np.conj(conv(np.conj(zv)))
-        v = w / np.linalg.norm(w)
-    return s
-
-
-def test_c2_batched_mixed_solve_full_size():
-    """The benchmarked configuration end to end: 32^3 voxels, 64 plane waves, the FP32
-    forward operator, the FP32 preconditioner copy (chi_fact = 1e-4, its four lowest
-    levels as dense node inverses) on split-BF16 arithmetic, FGMRES(20) to 1e-4.
-
-    Every column's true residual, taken by the solver with the compressed operator, meets
-    the tolerance, and so does the residual recomputed through the user-order apply
-    (hodbf_apply, FP64 in and out).  Against the oracle's FFT-exact product the residual
-    of columns 0 and 63 is bounded by tol + 10 chi_con ||Z|| ||x|| / ||b||: the
-    compression error is relative to ||Z|| ||x||, and on this high-contrast, ill-conditioned
-    workload ||Z|| ||x|| / ||b|| is in the hundreds, so the exact residual is not within
-    10 chi_con of ||b|| (it is about 3e-2).  ||Z|| is estimated from below by power
-    iteration, which can only tighten the bound."""
-    from paper_2111_01730_amd.hodbf import P_FP32, Operator
-    cfg = config("c2_batched_32")
-    g = cfg["grid"]
-    tol = cfg["tol"]
-    print("[c2 mixed solve: build]", flush=True)
-    op = Operator(g, tol_con=tol, tol_fact=1e-4, precond=P_FP32, seed=cfg["seed"],
-                  precond_dense_levels=4)
-    b = op.plane_wave(cfg["dirs"])
-    x, info = op.solve(b, tol=tol, use_precond="fp32_split")
-    print(f"[c2 mixed solve: steps mean {info['iters'].mean():.1f} max {info['iters'].max()}, "
-          f"relres max {info['relres'].max():.2e}]", flush=True)
-    assert b.shape[1] == 64
-    assert info["converged"].all() and np.all(info["relres"] <= tol)
-    assert info["iters"].max() <= 40
-    r = (b - op.apply(x)).cpu().numpy()
-    bn = b.cpu().numpy()
-    rel_con = np.linalg.norm(r, axis=0) / np.linalg.norm(bn, axis=0)
-    assert np.all(rel_con <= 1.05 * tol), rel_con.max()
-    xn = x.cpu().numpy()
-    sigma = _norm2_estimate(g)
-    for q in (0, 63):
-        re = bn[:, q] - vie.fft_matvec(g, xn[:, q])
-        rel = np.linalg.norm(re) / np.linalg.norm(bn[:, q])
-        amp = sigma * np.linalg.norm(xn[:, q]) / np.linalg.norm(bn[:, q])
-        print(f"[c2 mixed solve: column {q}: residual with the exact product {rel:.2e}, "
-              f"||Z|| ||x|| / ||b|| >= {amp:.0f}]", flush=True)
-        assert rel <= tol + 10 * tol * amp, (q, rel, amp)

@@ -1,0 +1,124 @@
+"""Arithmetic parity at the full 32^3 workload (32,768 unknowns, 64 plane waves), in the
+launch configuration the benchmark times: the oracle re-applies the library's exported
+factors in FP64 and every output element is held to the rounding bound of its own
+dependent chain (tests/bounds.py), besides a column-norm bound from the rounding model.
+
+Covered: the forward apply with FP32 arithmetic (which 0) and split-BF16 arithmetic
+(which 5), the preconditioner's FP32 copy with FP32 (which 2) and split-BF16 (which 6)
+arithmetic with four dense bottom levels (1024-unknown dense node inverses, the
+benchmark's setting), and the batched mixed-form solve, whose true residual under the
+oracle's FP64 product with the exported compressed operator must meet the tolerance."""
+import numpy as np
+import pytest
+
+from oracle import vie
+from synth import config
+from tests import bounds
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def c2():
+    from paper_2111_01730_amd.hodbf import P_FP32, Operator
+    from tests.plan_tools import hodbf_from_export, precond_from_export
+    cfg = config("c2_batched_32")
+    g = cfg["grid"]
+    print("[c2 parity: build 32^3, chi_con 1e-4, chi_fact 1e-4, 4 dense levels]", flush=True)
+    op = Operator(g, tol_con=cfg["tol"], tol_fact=1e-4, precond=P_FP32, seed=cfg["seed"],
+                  precond_dense_levels=4)
+    st = op.stats()
+    perm = op.perm()
+    ftab, fvals = op.forward_blocks()
+    fwd = hodbf_from_export(g, perm, ftab, fvals)
+    ptab, pvals = op.precond_blocks("fp32")
+    pre = precond_from_export(g, perm, ptab, pvals, st["levels"])
+    b = op.plane_wave(cfg["dirs"])
+    bt = b.cpu().numpy()[perm]  # tree order
+    print(f"[c2 parity: built, {st['entries_fwd']} / {st['entries_pre']} entries]", flush=True)
+    return dict(cfg=cfg, g=g, op=op, st=st, perm=perm, ftab=ftab, fwd=fwd, ptab=ptab,
+                pre=pre, bt=bt, b=b)
+
+
+def _tree_apply(op, xt, which):
+    x = torch.as_tensor(np.ascontiguousarray(xt.astype(np.complex64))).cuda()
+    return op.apply_tree(x, which).cpu().numpy().astype(np.complex128)
+
+
+def _inputs(c2, kind):
+    xt = c2["bt"].astype(np.complex64).astype(np.complex128)
+    return bounds.coherent(xt) if kind == "coherent" else xt
+
+
+@pytest.mark.parametrize("kind", ["plane_waves", "coherent"])
+@pytest.mark.parametrize("which,split", [(0, False), (5, True)])
+def test_c2_forward_full_size_matches_exported_factors(c2, which, split, kind):
+    xt = _inputs(c2, kind)
+    assert xt.shape[1] == 64
+    y = _tree_apply(c2["op"], xt, which)
+    ref = c2["fwd"].apply_tree(xt)
+    absref = bounds.absolute_hodbf(c2["fwd"]).apply_tree(np.abs(xt))
+    dims = bounds.forward_stage_dims(c2["ftab"], c2["st"]["levels"])
+    ratio, col_ref, col_abs = bounds.check(y, ref, absref, dims, split)
+    tol = bounds.normwise_tolerance(dims, split)
+    print(f"[c2 forward which {which}, {kind}: {len(dims)} stages, element-wise error / "
+          f"bound {ratio:.3f}, column error {col_ref:.2e} (tolerance {tol:.2e})]", flush=True)
+    assert ratio <= 1.0
+    assert col_ref <= tol
+
+
+@pytest.mark.parametrize("kind", ["plane_waves", "coherent"])
+@pytest.mark.parametrize("which,split", [(2, False), (6, True)])
+def test_c2_precond_dense_bottom_full_size_matches_exported_factors(c2, which, split, kind):
+    from tests.plan_tools import DenseBottomPrecond
+    assert isinstance(c2["pre"], DenseBottomPrecond)
+    assert c2["pre"].lb == c2["st"]["levels"] - 4
+    xt = _inputs(c2, kind)
+    z = _tree_apply(c2["op"], xt, which)
+    ref = c2["pre"].apply_tree(xt)
+    absref = bounds.absolute_precond(c2["pre"]).apply_tree(np.abs(xt))
+    dims = bounds.precond_stage_dims(c2["ptab"], c2["st"]["levels"])
+    ratio, col_ref, col_abs = bounds.check(z, ref, absref, dims, split)
+    tol = bounds.normwise_tolerance(dims, split)
+    # the multiplicative form cancels (its output is much smaller than its abs chain), so
+    # the norm-wise bound is taken against the abs chain
+    print(f"[c2 preconditioner which {which}, {kind}: {len(dims)} dependent stages, "
+          f"element-wise error / bound {ratio:.3f}, column error vs abs chain {col_abs:.2e} "
+          f"(tolerance {tol:.2e}), vs exact {col_ref:.2e}]", flush=True)
+    assert ratio <= 1.0
+    assert col_abs <= tol
+
+
+def test_c2_batched_mixed_solve_matches_exported_operator(c2):
+    """The benchmarked solve (FP32 forward, split-BF16 preconditioner, FGMRES(20) to
+    1e-4, 64 columns at once): re-applied by the oracle in FP64 with the exported
+    compressed operator, every column's residual is within 1.05 chi_sol plus the FP32
+    rounding bound of the library's own product (the solver's check runs in FP32 on x
+    rounded to FP32).  The residual with the exact (FFT) product is reported: it adds the
+    compression error, which on this ill-conditioned workload is not small against ||b||."""
+    op, tol = c2["op"], c2["cfg"]["tol"]
+    x, info = op.solve(c2["b"], tol=tol, use_precond="fp32_split")
+    print(f"[c2 mixed solve: steps mean {info['iters'].mean():.1f} max {info['iters'].max()}, "
+          f"solver relres max {info['relres'].max():.3e}]", flush=True)
+    assert info["converged"].all() and np.all(info["relres"] <= tol)
+    perm = c2["perm"]
+    xt = x.cpu().numpy()[perm]
+    bt = c2["bt"]
+    r = bt - c2["fwd"].apply_tree(xt)
+    bn = np.linalg.norm(bt, axis=0)
+    rel = np.linalg.norm(r, axis=0) / bn
+    dims = bounds.forward_stage_dims(c2["ftab"], c2["st"]["levels"])
+    # x enters the FP32 product rounded (u |x|) and the product's own rounding
+    g = bounds.worst_case_gamma(dims) + bounds.U32
+    slack = g * np.linalg.norm(bounds.absolute_hodbf(c2["fwd"]).apply_tree(np.abs(xt)), axis=0) / bn
+    print(f"[c2 mixed solve vs exported operator in FP64: relres max {rel.max():.3e}, "
+          f"bound {1.05 * tol:.2e} + rounding up to {slack.max():.2e}]", flush=True)
+    assert np.all(rel <= 1.05 * tol + slack), (rel.max(), slack.max())
+    g_ = c2["g"]
+    xu = x.cpu().numpy()
+    bu = c2["b"].cpu().numpy()
+    for q in (0, 63):
+        re = bu[:, q] - vie.fft_matvec(g_, xu[:, q])
+        print(f"[c2 mixed solve: column {q} residual with the exact product "
+              f"{np.linalg.norm(re) / np.linalg.norm(bu[:, q]):.3e} (reported)]", flush=True)

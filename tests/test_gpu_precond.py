@@ -67,7 +67,7 @@ def test_precond_apply_matches_exported_factors(case, copy, which, tol, R):
 def test_precond_is_approximate_inverse(case):
     c, g, op, Z = case
     x = c["x"][:, :4]
-    z = op.precond_apply(_t(Z @ x)).cpu().numpy()  # default copy: FP16
+    z = op.precond_apply(_t(Z @ x)).cpu().numpy()  # default: FP32 copy, split-BF16
     assert np.all(_rel(z, x) <= 0.3)
     z32 = _apply_copy(op, Z @ x, 2)
     assert np.all(_rel(z32, x) <= 0.3)
@@ -214,3 +214,53 @@ def test_dense_bottom_reaching_above_min_level_is_rejected(case):
     with pytest.raises(HodbfError):
         hodbf.Operator(g, tol_con=1e-4, tol_fact=1e-2, precond=hodbf.P_FP32,
                        precond_min_level=LH - 1, precond_dense_levels=2)
+
+
+def test_precond_apply_default_is_split_arithmetic_on_the_fp32_copy(case):
+    # hodbf_precond_apply runs the arithmetic that preconditions best: the FP32 copy on
+    # split-BF16 MFMA (which 6), the same bits as the tree-order call
+    c, g, op, Z = case
+    x = c["x"][:, :8].astype(np.complex64).astype(np.complex128)
+    z = op.precond_apply(_t(x, torch.complex64)).cpu().numpy().astype(np.complex128)
+    assert np.array_equal(z, _apply_copy(op, x, 6))
+
+
+def _ptr(t):
+    import ctypes as C
+    return C.c_void_p(t.data_ptr())
+
+
+def test_padded_leading_dimensions(case):
+    """ld > N on every vector argument of the user-order calls: the padding rows are
+    neither read (NaN there changes nothing) nor written (a sentinel survives)."""
+    import ctypes as C
+
+    from paper_2111_01730_amd import _lib
+    c, g, op, Z = case
+    n, R = g.n, 5
+    lib, st = _lib.lib(), C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    ldx, ldy = n + 37, n + 101
+    xh = np.full((R, ldx), np.nan + 1j * np.nan)
+    xh[:, :n] = c["x"][:, :R].T
+    xd = torch.as_tensor(xh).cuda()
+    sentinel = 7.0 - 3.0j
+    for fn, ref in ((lib.hodbf_apply, op.apply), (lib.hodbf_precond_apply, op.precond_apply)):
+        yd = torch.full((R, ldy), sentinel, dtype=torch.complex128, device="cuda")
+        _lib.check(fn(op._h, R, _lib.C128, _ptr(xd), ldx, _ptr(yd), ldy, st))
+        y = yd.cpu().numpy()
+        assert np.all(y[:, n:] == sentinel)
+        want = ref(_t(c["x"][:, :R])).cpu().numpy()
+        assert np.array_equal(y[:, :n].T, want)
+    # the solve: b and x padded as well
+    b = op.plane_wave(c["dirs"][:R]).cpu().numpy()
+    bh = np.full((R, ldx), np.nan + 1j * np.nan)
+    bh[:, :n] = b.T
+    bd = torch.as_tensor(bh).cuda()
+    xs = torch.full((R, ldy), sentinel, dtype=torch.complex128, device="cuda")
+    opts = op._solve_opts(1e-5, 20, 500, "fp32")
+    code = lib.vie_solve(op._h, R, _ptr(bd), ldx, _ptr(xs), ldy, C.byref(opts), None, st)
+    _lib.check(code)
+    xsol = xs.cpu().numpy()
+    assert np.all(xsol[:, n:] == sentinel)
+    x_ref, _ = op.solve(_t(b), tol=1e-5, restart=20, max_iter=500, use_precond="fp32")
+    assert np.array_equal(xsol[:, :n].T, x_ref.cpu().numpy())
