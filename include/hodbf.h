@@ -259,6 +259,21 @@ hodbf_status hodbf_set_allocator(hodbf_alloc_fn alloc, hodbf_free_fn release, vo
 hodbf_status hodbf_plan_probe(const hodbf_build_params *params, int32_t which, void *buf,
                               size_t *bytes);
 
+/*
+ * hodbf_precond_probe -- run the preconditioner construction on the host only (complex
+ * FP64 on the CPU, no GPU): the forward plan as hodbf_plan_probe, then Algorithm 1
+ * (Section III-B) with the butterfly Sherman-Morrison-Woodbury recursion of Algorithm 2
+ * and every new butterfly reconstructed from products with structured random vectors,
+ * exactly the steps hodbf_build runs on the device.  For verification of that host
+ * logic on small problems (N <= 65536, else E_ARG).  which: 0 perm (int32 N); 3 block
+ * table (as hodbf_export 3: leaf inverses as kind 0 rows, then the X_tau butterflies);
+ * 4 values (complex FP64); 7 counters (int64: reconstructions, Woodbury inversions,
+ * sketch columns, interpolative decompositions, largest rank, operator products).
+ * Same size protocol as hodbf_export; results are cached for the last parameter set.
+ */
+hodbf_status hodbf_precond_probe(const hodbf_build_params *params, int32_t which, void *buf,
+                                 size_t *bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -83,6 +83,7 @@ def lib():
     L.hodbf_stats.argtypes = [vp, C.POINTER(Stats)]
     L.hodbf_export.argtypes = [vp, i32, vp, C.POINTER(C.c_size_t)]
     L.hodbf_plan_probe.argtypes = [C.POINTER(BuildParams), i32, vp, C.POINTER(C.c_size_t)]
+    L.hodbf_precond_probe.argtypes = [C.POINTER(BuildParams), i32, vp, C.POINTER(C.c_size_t)]
     L.hodbf_apply_tree.argtypes = [vp, i32, i32, vp, vp, vp]
     L.hodbf_set_allocator.argtypes = [ALLOC_FN, FREE_FN, vp]
     L.hodbf_free.argtypes = [vp]
@@ -90,7 +91,7 @@ def lib():
     L.hodbf_last_error.restype = C.c_char_p
     for name in ["hodbf_build", "hodbf_apply", "hodbf_precond_apply", "vie_solve", "hodbf_apply_tree",
                  "hodbf_plane_wave", "hodbf_solve_workspace", "hodbf_stats", "hodbf_export", "hodbf_plan_probe",
-                 "hodbf_set_allocator"]:
+                 "hodbf_precond_probe", "hodbf_set_allocator"]:
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -115,11 +116,12 @@ def make_params(grid, tol_con, tol_fact=0.0, leaf_size=64, precond_prec=P_NONE,
     return p
 
 
-def probe(params: BuildParams, which: int, dtype):
-    """Host-only plan export (no GPU needed)."""
-    L = lib()
+def probe(params: BuildParams, which: int, dtype, entry="hodbf_plan_probe"):
+    """Host-only export (no GPU needed): the forward plan (hodbf_plan_probe) or the
+    host run of the preconditioner construction (hodbf_precond_probe)."""
+    fn = getattr(lib(), entry)
     n = C.c_size_t(0)
-    check(L.hodbf_plan_probe(C.byref(params), which, None, C.byref(n)))
+    check(fn(C.byref(params), which, None, C.byref(n)))
     out = np.empty(n.value // np.dtype(dtype).itemsize, dtype=dtype)
-    check(L.hodbf_plan_probe(C.byref(params), which, out.ctypes.data_as(C.c_void_p), C.byref(n)))
+    check(fn(C.byref(params), which, out.ctypes.data_as(C.c_void_p), C.byref(n)))
     return out

@@ -10,6 +10,7 @@
 #include <mutex>
 
 #include "pack_sink.h"
+#include "precond_host.h"
 
 namespace hodbf {
 
@@ -43,22 +44,7 @@ void hip_check(hipError_t e, const char *what) {
 
 template <typename F>
 static hodbf_status guarded(F &&f) {
-  try {
-    f();
-    return HODBF_OK;
-  } catch (const Error &e) {
-    set_last_error(e.msg);
-    return e.code;
-  } catch (const std::bad_alloc &) {
-    set_last_error("host allocation failed");
-    return HODBF_E_NOMEM;
-  } catch (const std::exception &e) {
-    set_last_error(e.what());
-    return HODBF_E_HIP;
-  } catch (...) {
-    set_last_error("unknown internal error");
-    return HODBF_E_HIP;
-  }
+  return hodbf_guarded(std::forward<F>(f));
 }
 
 // ---------------------------------------------------------------------------

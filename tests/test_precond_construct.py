@@ -1,0 +1,90 @@
+"""The library's preconditioner construction (Algorithm 1 with the butterfly
+Sherman-Morrison-Woodbury recursion of Algorithm 2, every new butterfly reconstructed
+from products with structured random vectors), run on the host through
+hodbf_precond_probe (complex FP64, no GPU) and checked against the oracle:
+
+* chi -> 0 (compression and factorization at 1e-10): P is Z^{-1} up to the FP32 storage
+  of its factors, and equals the oracle's multiplicative inverse (Algorithm 1 computed
+  densely) to the same level;
+* at chi_fact = 1e-2 and 1e-4 on a ragged grid: ||P Z x - x|| is of the size of the
+  oracle's own (the same tolerance gives the same quality), and P differs from the
+  oracle's P by O(chi_fact);
+* the number of reconstructions is what the recursion of Algorithm 2 predicts (one for
+  line 7 of Algorithm 1 per level, then per BF_SMW call: A22^{-1}, the Schur update
+  and A11^{-1} recursively, and the final product)."""
+import numpy as np
+import pytest
+
+from oracle import precond as oprecond
+from oracle import vie
+from synth.workloads import small_case
+
+_lib = pytest.importorskip("paper_2111_01730_amd._lib")
+
+
+def _probe(g, chi_con, chi_fact, seed=1):
+    from tests.plan_tools import precond_from_export
+    p = _lib.make_params(g, chi_con, chi_fact, precond_prec=1, seed=seed)
+    perm = _lib.probe(p, 0, np.int32, "hodbf_precond_probe")
+    tab = _lib.probe(p, 3, np.int64, "hodbf_precond_probe").reshape(-1, 12)
+    vals = _lib.probe(p, 4, np.complex128, "hodbf_precond_probe")
+    stats = _lib.probe(p, 7, np.int64, "hodbf_precond_probe")
+    depth = int(tab[tab[:, 0] == 0][0, 1])
+    return precond_from_export(g, perm, tab, vals, depth), stats, depth
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b, axis=0) / np.linalg.norm(b, axis=0)
+
+
+def test_tight_tolerances_give_the_inverse():
+    c = small_case(61, sides=(8, 8, 8), h=0.1, eps_range=(2.0, 6.0), loss=0.3, nrhs=4)
+    g = c["grid"]
+    P, stats, _ = _probe(g, 1e-10, 1e-10)
+    Z = vie.dense(g)
+    x = c["x"]
+    assert np.all(_rel(P.apply(Z @ x), x) <= 1e-6)  # FP32 storage of the factors
+    po = oprecond.build_precond(g, 1e-10)
+    assert np.all(_rel(P.apply(x), po.apply(x)) <= 1e-6)
+
+
+@pytest.fixture(scope="module")
+def ragged():
+    c = small_case(61, sides=(10, 9, 8), h=0.1, eps_range=(2.0, 8.0), loss=0.5, nrhs=6)
+    return c, vie.dense(c["grid"])
+
+
+@pytest.mark.parametrize("chi_fact", [1e-2, 1e-4])
+def test_quality_matches_the_oracle(ragged, chi_fact):
+    c, Z = ragged
+    g = c["grid"]
+    P, _, _ = _probe(g, 1e-6, chi_fact)
+    x = c["x"]
+    po = oprecond.build_precond(g, chi_fact)
+    mine = _rel(P.apply(Z @ x), x).max()
+    theirs = _rel(po.apply(Z @ x), x).max()
+    assert mine <= 3 * theirs, (mine, theirs)
+    # both approximate Z^{-1} to O(chi_fact) times the amplification of this grid
+    assert np.all(_rel(P.apply(x), po.apply(x)) <= 30 * chi_fact)
+
+
+def _predicted_reconstructions(depth):
+    def smw(lc, has22):
+        return inv(lc, has22) + inv(lc, True) + 1
+
+    def inv(lc, present):
+        if not present:
+            return 0
+        if lc - 2 < 0:
+            return 1
+        return 1 + smw(lc - 2, True)
+
+    return sum(1 + smw(depth - l - 1, False) for l in range(depth))
+
+
+@pytest.mark.parametrize("sides", [(8, 8, 8), (10, 9, 8), (16, 16, 8)])
+def test_reconstruction_count_follows_algorithm_2(sides):
+    c = small_case(7, sides=sides, h=0.1, eps_range=(2.0, 4.0), loss=0.1, nrhs=1)
+    _, stats, depth = _probe(c["grid"], 1e-4, 1e-2)
+    assert int(stats[0]) == _predicted_reconstructions(depth)
+    assert _predicted_reconstructions(3) == 12 and _predicted_reconstructions(4) == 18
