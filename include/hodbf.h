@@ -209,6 +209,9 @@ typedef struct {
                                 (blocks that read the same rows share them); one apply reads
                                 and writes 8 * nrhs * io_rows_fwd vector bytes */
   int64_t io_rows_pre;       /* the same for the preconditioner */
+  int64_t precond_reconstructions; /* butterfly sets rebuilt from random-vector products
+                                      (Algorithm 1 line 7 and every BF_SMW step) */
+  int64_t precond_sketch_cols;     /* columns of all those random-vector products */
 } hodbf_stats_t;
 
 hodbf_status hodbf_stats(const hodbf_op *op, hodbf_stats_t *st);
@@ -269,6 +272,8 @@ hodbf_status hodbf_plan_probe(const hodbf_build_params *params, int32_t which, v
  * table (as hodbf_export 3: leaf inverses as kind 0 rows, then the X_tau butterflies);
  * 4 values (complex FP64); 7 counters (int64: reconstructions, Woodbury inversions,
  * sketch columns, interpolative decompositions, largest rank, operator products).
+ * which + 16: the same exports, with every butterfly set packed into the device path's
+ * grouped-GEMM programs (forward and transposed) and run by a host interpreter of them.
  * Same size protocol as hodbf_export; results are cached for the last parameter set.
  */
 hodbf_status hodbf_precond_probe(const hodbf_build_params *params, int32_t which, void *buf,

@@ -58,7 +58,7 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError("hodbf build failed:\n" + "\n".join(errors))
     tmp = LIB + ".tmp"
     link = [hipcc, "-shared", "-fPIC", "-fopenmp", "-o", tmp] + objs + [
-        f"-L{ROCM}/lib", "-lrocblas", "-lrocsolver",
+        f"-L{ROCM}/lib",
         f"-Wl,-rpath,{ROCM}/lib", f"-Wl,-rpath,{ROCM}/llvm/lib",
     ]
     if verbose:

@@ -50,7 +50,8 @@ class Stats(C.Structure):
                 ("bytes_fwd", C.c_int64), ("bytes_pre", C.c_int64), ("bytes_total", C.c_int64),
                 ("fwd_stages", C.c_int32), ("pre_stages", C.c_int32),
                 ("build_seconds", C.c_double), ("precond_seconds", C.c_double),
-                ("id_count", C.c_int64), ("io_rows_fwd", C.c_int64), ("io_rows_pre", C.c_int64)]
+                ("id_count", C.c_int64), ("io_rows_fwd", C.c_int64), ("io_rows_pre", C.c_int64),
+                ("precond_reconstructions", C.c_int64), ("precond_sketch_cols", C.c_int64)]
 
 
 class HodbfError(RuntimeError):

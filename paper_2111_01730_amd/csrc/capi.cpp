@@ -222,7 +222,7 @@ static void pack_forward(hodbf_op &op, FwdPlan &fp, hipStream_t st) {
                  op.ker.kh, k2S, op.fwdF.as<float2>(), nullptr, st);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));
-  upload_program(op.fwd, pk, st);
+  upload_program(op.fwd, pk, st, true, op.n, total);
   int64_t ent = 0;
   for (auto &r : op.fwd_table) ent += r.m * r.n;
   op.fwd_entries = ent;
@@ -255,10 +255,10 @@ hodbf_status hodbf_build(const hodbf_build_params *params, hodbf_op **out) {
     op->id_count = fp.id_count;
     upload_geometry(*op, st);
     pack_forward(*op, fp, st);
-    fp.bfs.clear();
     op->build_seconds =
         std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    if (params->precond_prec != HODBF_P_NONE) build_precond(*op, st);
+    if (params->precond_prec != HODBF_P_NONE) build_precond(*op, fp.bfs, st);
+    fp.bfs.clear();
     *out = op.release();
   });
 }
@@ -414,6 +414,8 @@ hodbf_status hodbf_stats(const hodbf_op *op, hodbf_stats_t *s) {
     s->precond_seconds = op->pre.seconds;
     s->id_count = op->id_count;
     s->io_rows_fwd = op->fwd.io_rows;
+    s->precond_reconstructions = op->pre.reconstructions;
+    s->precond_sketch_cols = op->pre.sketch_cols;
     s->io_rows_pre = op->pre.leaf.io_rows;
     for (auto &lv : op->pre.levels) s->io_rows_pre += lv.prog.io_rows;
   });

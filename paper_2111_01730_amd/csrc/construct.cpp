@@ -337,47 +337,84 @@ uint64_t mix(uint64_t a, uint64_t b) {
   return z;
 }
 
-// Drop outputs of transfer blocks that read nothing (a zero-rank input side leaves a
-// block with columns of rank 0 only): their rows would never be written, so the rows
-// and the matching columns of their consumers are removed.
-void prune(Butterfly &bf) {
+void drop_cols(Mat &f, int c0, int cnt) {
+  if (cnt == 0) return;
+  std::vector<cf> nv;
+  if (f.m > 0) {
+    nv.reserve(size_t(f.m) * size_t(f.n - cnt));
+    for (int k = 0; k < f.n; ++k) {
+      if (k >= c0 && k < c0 + cnt) continue;
+      nv.insert(nv.end(), f.v.begin() + size_t(k) * f.m, f.v.begin() + size_t(k + 1) * f.m);
+    }
+  }
+  f.v.swap(nv);
+  f.n -= cnt;
+}
+
+// rank (output rows) of block idx at stage s (0: V^0)
+Mat &stage_block(Butterfly &bf, int s, int64_t idx) {
+  return s == 0 ? bf.V0[size_t(idx)] : bf.W[size_t(s)][size_t(idx)];
+}
+
+// Remove the rows of stage block (s, (a, b)) and the matching columns of its readers.
+void drop_rows(Butterfly &bf, int s, int64_t a, int64_t b) {
   const int L = bf.L;
-  for (int l = 1; l <= L; ++l) {
-    const int64_t na = int64_t(1) << l, nb = int64_t(1) << (L - l);
-    for (int64_t a = 0; a < na; ++a)
-      for (int64_t b = 0; b < nb; ++b) {
-        Mat &w = bf.W[size_t(l)][size_t(a * nb + b)];
-        if (w.n > 0 || w.m == 0) continue;
-        const int m = w.m;
-        w.m = 0;
-        w.v.clear();
-        // consumers: stage l + 1 blocks (2a + c, b / 2) reading it as part (b & 1), or B[a]
-        auto drop_cols = [&](Mat &f, int c0, int cnt) {
-          std::vector<cf> nv;
-          nv.reserve(size_t(f.m) * size_t(f.n - cnt));
-          for (int k = 0; k < f.n; ++k) {
-            if (k >= c0 && k < c0 + cnt) continue;
-            nv.insert(nv.end(), f.v.begin() + size_t(k) * f.m, f.v.begin() + size_t(k + 1) * f.m);
-          }
-          f.v.swap(nv);
-          f.n -= cnt;
-        };
-        if (l == L) {
-          drop_cols(bf.B[size_t(a)], 0, m);
-        } else {
-          const int64_t nb2 = nb / 2;
-          const int part = int(b & 1);
-          const int first = part == 0 ? 0 : bf.W[size_t(l)][size_t(a * nb + (b & ~int64_t(1)))].m;
-          for (int c = 0; c < 2; ++c) {
-            Mat &f = bf.W[size_t(l + 1)][size_t((2 * a + c) * nb2 + b / 2)];
-            if (f.n >= first + m) drop_cols(f, first, m);
-          }
-        }
-      }
+  const int64_t nb = int64_t(1) << (L - s);
+  Mat &w = stage_block(bf, s, a * nb + b);
+  const int m = w.m;
+  if (m == 0) return;
+  w.m = 0;
+  w.v.clear();
+  if (s == L) {
+    drop_cols(bf.B[size_t(a)], 0, m);
+    return;
+  }
+  const int64_t nb2 = nb / 2;
+  const int first = (b & 1) ? stage_block(bf, s, a * nb + (b & ~int64_t(1))).m : 0;
+  for (int c = 0; c < 2; ++c) {
+    Mat &f = bf.W[size_t(s + 1)][size_t((2 * a + c) * nb2 + b / 2)];
+    if (f.n >= first + m) drop_cols(f, first, m);
   }
 }
 
 }  // namespace
+
+// Keep every stage row both written and read: a transfer block that reads nothing
+// (its inputs all have rank 0) outputs zeros, and a stage output that no later block
+// reads is dead; both lose their rows (and the matching columns downstream), until
+// nothing changes.  The product is unchanged.
+void prune_butterfly(Butterfly &bf) {
+  const int L = bf.L;
+  for (bool changed = true; changed;) {
+    changed = false;
+    for (int s = 1; s <= L; ++s) {
+      const int64_t na = int64_t(1) << s, nb = int64_t(1) << (L - s);
+      for (int64_t a = 0; a < na; ++a)
+        for (int64_t b = 0; b < nb; ++b) {
+          const Mat &w = bf.W[size_t(s)][size_t(a * nb + b)];
+          if (w.m > 0 && w.n == 0) {
+            drop_rows(bf, s, a, b);
+            changed = true;
+          }
+        }
+    }
+    for (int s = 0; s < L; ++s) {
+      const int64_t na = int64_t(1) << s, nb = int64_t(1) << (L - s);
+      for (int64_t a = 0; a < na; ++a)
+        for (int64_t b = 0; b < nb; ++b) {
+          if (stage_block(bf, s, a * nb + b).m == 0) continue;
+          const int64_t nb2 = nb / 2;
+          bool read = false;
+          for (int c = 0; c < 2; ++c)
+            read = read || bf.W[size_t(s + 1)][size_t((2 * a + c) * nb2 + b / 2)].m > 0;
+          if (!read) {
+            drop_rows(bf, s, a, b);
+            changed = true;
+          }
+        }
+    }
+  }
+}
 
 OpP chain(std::vector<OpP> ops) { return std::make_shared<Chain>(std::move(ops)); }
 OpP lincomb(std::vector<std::pair<cd, OpP>> t) { return std::make_shared<LinComb>(std::move(t)); }
@@ -728,7 +765,7 @@ std::vector<Butterfly> reconstruct(Engine &E, const LinOp &M, int lev, int L,
         bf.B[size_t(a)] = to_mat(U, m, r);
       }
     }
-    prune(bf);
+    prune_butterfly(bf);
   }
   return out;
 }
@@ -876,6 +913,7 @@ PrecondBuild invert_hodbf(Engine &E, const Kernel &ker, int min_level,
     pb.leaf_inv[size_t(g)].D = to_mat(D, m, m);
   }
   OpP leaf = E.dense_diag(pb.leaf_inv);
+  pb.leaf_op = leaf;
   std::vector<OpP> built;
   for (int l = LH - 1; l >= min_level; --l) {
     auto tl = std::chrono::steady_clock::now();
@@ -900,6 +938,7 @@ PrecondBuild invert_hodbf(Engine &E, const Kernel &ker, int min_level,
     std::vector<Butterfly> X = smw(c, nodes, l, Lb, nullptr, E12, E21, nullptr);
     built.push_back(E.butterflies(X));
     pb.levels.push_back(std::move(X));
+    pb.ops.push_back(built.back());
     logf("preconditioner level %d: %lld nodes, %.2f s (%.2f s so far), %lld reconstructions, "
          "%lld sketch columns", l, (long long)nodes.size(), seconds_since(tl), seconds_since(t0),
          (long long)pb.reconstructions, (long long)pb.stats.sketch_cols);

@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "sketch_rng.h"
 
 namespace hodbf {
 
@@ -70,6 +71,8 @@ class Engine {
   // 0 elsewhere.  slot_of_row[r] < 0: the row carries no slot.
   virtual void fill_sketch(Mv &x, const std::vector<int32_t> &slot_of_row, int64_t col0, int k,
                            uint64_t seed) = 0;
+  // x(r, q) = 1 where q == col_of_row[r], 0 elsewhere (unit probes)
+  virtual void fill_unit(Mv &x, const std::vector<int32_t> &col_of_row) = 0;
   // all requests into out, back to back (k values per gathered row)
   virtual void gather(const Mv &y, const std::vector<Gather> &req, int k,
                       std::vector<cd> &out) = 0;
@@ -78,21 +81,16 @@ class Engine {
 };
 
 // The random value fill_sketch writes at (row r, global column g): host and device use
-// the same integer hash, so the host can regenerate any sketch entry exactly.
-inline uint64_t sketch_hash(uint64_t seed, uint64_t r, uint64_t g) {
-  uint64_t z = seed ^ (r * 0x9E3779B97F4A7C15ull) ^ (g * 0xD1B54A32D192ED03ull);
-  z ^= z >> 30;
-  z *= 0xBF58476D1CE4E5B9ull;
-  z ^= z >> 27;
-  z *= 0x94D049BB133111EBull;
-  z ^= z >> 31;
-  return z;
-}
+// the same integer hash (sketch_rng.h), so the host can regenerate any sketch entry.
 inline cd sketch_value(uint64_t seed, uint64_t r, uint64_t g) {
-  const uint64_t h = sketch_hash(seed, r, g);
-  const double s = 0.70710678118654752440;
-  return cd((h & 1) ? -s : s, (h & 2) ? -s : s);
+  double re, im;
+  sketch_parts(seed, r, g, re, im);
+  return cd(re, im);
 }
+
+// Drop stage rows that are never written (blocks reading only rank-0 inputs) or never
+// read (outputs no later block uses), with the matching columns downstream.
+void prune_butterfly(Butterfly &bf);
 
 // ---- composite operators (backend independent) ----
 OpP chain(std::vector<OpP> ops);                 // y = ops.back() ... ops[0] x
@@ -142,6 +140,8 @@ std::vector<Butterfly> reconstruct(Engine &E, const LinOp &M, int lev, int L,
 struct PrecondBuild {
   std::vector<DenseDiag> leaf_inv;
   std::vector<std::vector<Butterfly>> levels;  // levels[i] is tree level L_H - 1 - i
+  OpP leaf_op;              // the leaf inverses as the engine's operator
+  std::vector<OpP> ops;     // X of each built level as the engine's operator (same order)
   RbfStats stats;
   int64_t reconstructions = 0, woodbury = 0;
 };
@@ -153,7 +153,9 @@ PrecondBuild invert_hodbf(Engine &E, const Kernel &ker, int min_level,
 // level already built (levels in build order, i.e. towards the root).
 OpP mult_inverse(Engine &E, OpP leaf, const std::vector<OpP> &levels);
 
-// Host engine: complex FP64 on the CPU (small problems; tests and verification).
-std::unique_ptr<Engine> make_host_engine(const Tree *t, int max_cols = 512);
+// Host engine: complex FP64 on the CPU (small problems; tests and verification).  With
+// programs = true its butterfly sets are packed into the device path's grouped-GEMM
+// programs (forward and transposed) and run by a host interpreter of those descriptors.
+std::unique_ptr<Engine> make_host_engine(const Tree *t, int max_cols = 512, bool programs = false);
 
 }  // namespace hodbf

@@ -2,8 +2,11 @@
 // CPU, butterflies and dense blocks applied by plain loops.  It runs the same Algorithm
 // 1 / Algorithm 2 code as the device engine, for small problems and verification.
 #include <algorithm>
+#include <cmath>
+#include <limits>
 
 #include "construct.h"
+#include "pack_sink.h"
 
 namespace hodbf {
 
@@ -150,9 +153,53 @@ class HostDense final : public LinOp {
   std::vector<DenseDiag> b_;
 };
 
+// The packed grouped-GEMM programs of the device path, run by a host interpreter with
+// the kernels' semantics: every tile sums its pairs (factor column-major at f_off with
+// lda, times input rows of X or T) and scatters its rows through the row map into T or
+// OUT (beta 0 stores, beta 1 adds).  T starts as NaN, so a read of a row no earlier
+// launch wrote poisons the result.
+class HostProgOp final : public LinOp {
+ public:
+  PackSink fwd, trans;
+  std::vector<cd> arena;
+  void apply(Engine &E, bool tr, const Mv &x, Mv &y) const override {
+    const PackSink &pk = tr ? trans : fwd;
+    const int R = x.R;
+    const auto &X = hv(x).d;
+    auto &Y = hv(y).d;
+    std::fill(Y.begin(), Y.end(), cd(0, 0));
+    std::vector<cd> T(size_t(std::max<int64_t>(pk.t_rows, 1)) * R,
+                      cd(std::numeric_limits<double>::quiet_NaN(), 0.0));
+    std::vector<cd> acc;
+    for (const Launch &ln : pk.launches)
+      for (int64_t s = ln.s0; s < ln.s0 + ln.ns; ++s) {
+        const Seg &sg = pk.segs[size_t(s)];
+        acc.assign(size_t(sg.m) * R, cd(0, 0));
+        for (int32_t p = sg.p0; p < sg.p1; ++p) {
+          const Pair &pr = pk.pairs[size_t(p)];
+          const cd *in = (pr.in_buf ? T.data() : X.data()) + size_t(pr.in_row) * R;
+          for (int k = 0; k < pr.n; ++k)
+            for (int i = 0; i < sg.m; ++i) {
+              const cd a = arena[size_t(pr.f_off + int64_t(k) * pr.lda + i)] * double(pr.scale);
+              for (int q = 0; q < R; ++q) acc[size_t(i) * R + q] += a * in[size_t(k) * R + q];
+            }
+        }
+        cd *dst = ln.out ? Y.data() : T.data();
+        for (int i = 0; i < sg.m; ++i) {
+          int32_t base = 0;
+          for (int32_t e = sg.map0; e < sg.map1; ++e)
+            if (pk.rowmap[size_t(e)].start <= i) base = pk.rowmap[size_t(e)].out_row - pk.rowmap[size_t(e)].start;
+          cd *o = dst + size_t(base + i) * R;
+          for (int q = 0; q < R; ++q) o[q] = ln.beta ? o[q] + acc[size_t(i) * R + q] : acc[size_t(i) * R + q];
+        }
+      }
+    (void)E;
+  }
+};
+
 class HostEngine final : public Engine {
  public:
-  HostEngine(const Tree *t, int mc) : mc_(mc) { tree = t; }
+  HostEngine(const Tree *t, int mc, bool programs) : mc_(mc), programs_(programs) { tree = t; }
   int max_cols() const override { return mc_; }
   MvP make(int R) override {
     auto m = std::make_shared<HostMv>();
@@ -190,6 +237,14 @@ class HostEngine final : public Engine {
       }
     }
   }
+  void fill_unit(Mv &x, const std::vector<int32_t> &col_of_row) override {
+    auto &X = hv(x).d;
+    std::fill(X.begin(), X.end(), cd(0, 0));
+    for (int64_t r = 0; r < n(); ++r) {
+      const int32_t c = col_of_row[size_t(r)];
+      if (c >= 0 && c < x.R) X[size_t(r) * x.R + size_t(c)] = 1.0;
+    }
+  }
   void gather(const Mv &y, const std::vector<Gather> &req, int k, std::vector<cd> &out) override {
     const auto &Y = hv(y).d;
     out.clear();
@@ -197,17 +252,52 @@ class HostEngine final : public Engine {
       for (int32_t r : g.rows)
         for (int i = 0; i < k; ++i) out.push_back(Y[size_t(r) * y.R + size_t(g.q0 + i)]);
   }
-  OpP butterflies(std::vector<Butterfly> bfs) override { return std::make_shared<HostBf>(tree, std::move(bfs)); }
+  OpP butterflies(std::vector<Butterfly> bfs) override {
+    if (!programs_) return std::make_shared<HostBf>(tree, std::move(bfs));
+    auto op = std::make_shared<HostProgOp>();
+    for (Butterfly &bf : bfs) prune_butterfly(bf);
+    std::vector<const Butterfly *> ptrs;
+    for (const Butterfly &bf : bfs) ptrs.push_back(&bf);
+    std::vector<BlockRec> table;
+    for (int dir = 0; dir < 2; ++dir) {
+      PackSink &pk = dir == 0 ? op->fwd : op->trans;
+      pk.table = &table;
+      pk.put_host = [&](const Mat &f, float *scale) { return put(op->arena, f, scale); };
+      if (dir == 0)
+        pack_group(pk, *tree, ptrs, false, 0, [](const Butterfly &, int64_t *md) {
+          md[0] = md[1] = md[2] = md[3] = 0;
+        });
+      else
+        pack_group_t(pk, *tree, ptrs);
+      check_program(pk, n(), -1);
+    }
+    for (int dir = 0; dir < 2; ++dir) {
+      PackSink &pk = dir == 0 ? op->fwd : op->trans;
+      retile(pk, kRetileBelow, kTileRows / 2);
+      check_program(pk, n(), int64_t(op->arena.size()));
+      pk.table = nullptr;
+      pk.put_host = nullptr;
+    }
+    return op;
+  }
   OpP dense_diag(std::vector<DenseDiag> blocks) override { return std::make_shared<HostDense>(std::move(blocks)); }
 
  private:
+  static int64_t put(std::vector<cd> &arena, const Mat &f, float *scale) {
+    *scale = 1.0f;
+    const int64_t off = (int64_t(arena.size()) + 15) & ~int64_t(15);
+    arena.resize(size_t(off + int64_t(f.m) * f.n), cd(0, 0));
+    for (size_t e = 0; e < f.v.size(); ++e) arena[size_t(off) + e] = cd(f.v[e]);
+    return off;
+  }
   int mc_;
+  bool programs_;
 };
 
 }  // namespace
 
-std::unique_ptr<Engine> make_host_engine(const Tree *t, int max_cols) {
-  return std::make_unique<HostEngine>(t, max_cols);
+std::unique_ptr<Engine> make_host_engine(const Tree *t, int max_cols, bool programs) {
+  return std::make_unique<HostEngine>(t, max_cols, programs);
 }
 
 }  // namespace hodbf

@@ -94,6 +94,7 @@ struct PrecondData {
   int max_rank = 0;
   int default_ft = FT_C64;
   double seconds = 0;
+  int64_t reconstructions = 0, sketch_cols = 0;  // randomized reconstructions, sketch columns
 };
 
 struct OpDevice {
@@ -157,7 +158,9 @@ class Scratch {
   void *ctx_ = nullptr;
 };
 
-void build_precond(hodbf_op &op, hipStream_t st);
+// Algorithm 1 / Algorithm 2 on the device; plan: the forward butterflies (host V0 / W
+// values and outer-factor skeletons) the construction reads B from.
+void build_precond(hodbf_op &op, const std::vector<Butterfly> &plan, hipStream_t st);
 
 // Pack a set of butterflies (stage launches + final reduce into leaf rows) into prog.
 struct PackInput {

@@ -10,6 +10,7 @@
 // maps scatter the rows back to each block's own output range.
 #include <algorithm>
 #include <functional>
+#include <map>
 #include <set>
 #include <tuple>
 
@@ -147,7 +148,13 @@ void retile(PackSink &pk, int64_t below, int rows) {
 void pack_group(PackSink &pk, const Tree &t, const std::vector<const Butterfly *> &bfs,
                 bool forward, int final_beta,
                 const std::function<void(const Butterfly &, int64_t *)> &meta) {
-  const int LH = t.depth;
+  // the leaf level of every butterfly of the set: the tree's leaves, or a coarser level
+  // for the butterflies of the inverse's recursion (their leaf clusters may exceed a tile)
+  int LH = t.depth;
+  if (!bfs.empty()) LH = bfs[0]->hod_level + bfs[0]->L;
+  for (auto *bf : bfs)
+    if (bf->hod_level + bf->L != LH) fail(HODBF_E_ARG, "butterflies of one program must share a leaf level");
+  if (forward && LH != t.depth) fail(HODBF_E_ARG, "dense leaf blocks need the tree's leaves");
   int Lmax = -1;
   for (auto *bf : bfs) Lmax = std::max(Lmax, bf->L);
   // off[k][s][idx]: first workspace row of output (a, b) at stage s of butterfly k
@@ -227,9 +234,7 @@ void pack_group(PackSink &pk, const Tree &t, const std::vector<const Butterfly *
   for (int64_t g = 0; g < nleaf; ++g) {
     const int32_t lo = t.node_lo(LH, g), hi = t.node_hi(LH, g);
     const int64_t m = hi - lo;
-    Seg sg{};
-    sg.m = int32_t(m);
-    sg.p0 = int32_t(pk.pairs.size());
+    const int64_t pair0 = int64_t(pk.pairs.size());
     if (forward) {
       Pair p{};
       p.scale = 1.0f;
@@ -269,10 +274,24 @@ void pack_group(PackSink &pk, const Tree &t, const std::vector<const Butterfly *
       if (pk.scales) pk.scales->push_back(p.scale);
       pk.pairs.push_back(p);
     }
-    sg.p1 = int32_t(pk.pairs.size());
-    if (sg.p1 > sg.p0) {
+    // one tile per kTileRows rows of the leaf, each with every pair (the first tile
+    // uses the pairs above; later ones copies whose column-major blocks start r0 rows
+    // further)
+    const int64_t pair1 = int64_t(pk.pairs.size());
+    if (pair1 == pair0) continue;
+    for (int64_t r0 = 0; r0 < m; r0 += kTileRows) {
+      Seg sg{};
+      sg.m = int32_t(std::min<int64_t>(kTileRows, m - r0));
+      sg.p0 = r0 == 0 ? int32_t(pair0) : int32_t(pk.pairs.size());
+      if (r0 > 0)
+        for (int64_t q = pair0; q < pair1; ++q) {
+          Pair pr = pk.pairs[size_t(q)];
+          pr.f_off += r0;
+          pk.pairs.push_back(pr);
+        }
+      sg.p1 = r0 == 0 ? int32_t(pair1) : int32_t(pk.pairs.size());
       sg.map0 = int32_t(pk.rowmap.size());
-      pk.rowmap.push_back({0, lo});
+      pk.rowmap.push_back({0, int32_t(lo + r0)});
       sg.map1 = int32_t(pk.rowmap.size());
       pk.segs.push_back(sg);
     }
@@ -281,8 +300,182 @@ void pack_group(PackSink &pk, const Tree &t, const std::vector<const Butterfly *
   if (ns > 0) pk.launches.push_back({seg0, ns, final_beta, 1});
 }
 
-void upload_program(Program &prog, PackSink &pk, hipStream_t st) {
+namespace {
+
+Mat transposed(const Mat &f) {
+  Mat t;
+  t.m = f.n;
+  t.n = f.m;
+  t.v.resize(f.v.size());
+  for (int k = 0; k < f.n; ++k)
+    for (int i = 0; i < f.m; ++i) t.v[size_t(i) * f.n + k] = f.v[size_t(k) * f.m + i];
+  return t;
+}
+
+// Tiles of at most kTileRows rows over an output block of `rows` rows at out_row of the
+// destination: every tile sums all the pairs (column-major factors: a tile's rows start
+// r0 further).
+void emit_sum(PackSink &pk, const std::vector<Pair> &pairs, int64_t out_row, int64_t rows) {
+  if (pairs.empty() || rows == 0) return;
+  for (int64_t r0 = 0; r0 < rows; r0 += kTileRows) {
+    Seg sg{};
+    sg.m = int32_t(std::min<int64_t>(kTileRows, rows - r0));
+    sg.p0 = int32_t(pk.pairs.size());
+    for (Pair p : pairs) {
+      p.f_off += r0;
+      pk.pairs.push_back(p);
+    }
+    sg.p1 = int32_t(pk.pairs.size());
+    sg.map0 = int32_t(pk.rowmap.size());
+    pk.rowmap.push_back({0, int32_t(out_row + r0)});
+    sg.map1 = int32_t(pk.rowmap.size());
+    pk.segs.push_back(sg);
+  }
+}
+
+}  // namespace
+
+// The transposed product y = M^T x of a set of butterflies sharing their level count:
+// the stages of pack_group in reverse with every factor transposed.  B^T blocks that
+// read the same row leaf are stacked; a transposed transfer stage sums the two
+// children's W^T contributions into one parent segment; the last launch sums the V^0
+// blocks of every butterfly reading a column leaf into its output rows (beta 0:
+// uncovered rows are left untouched).
+void pack_group_t(PackSink &pk, const Tree &t, const std::vector<const Butterfly *> &bfs) {
+  if (bfs.empty()) return;
+  const int L = bfs[0]->L, ll = bfs[0]->hod_level + L;
+  for (auto *bf : bfs)
+    if (bf->L != L || bf->hod_level + bf->L != ll)
+      fail(HODBF_E_ARG, "a transposed program needs butterflies of one shape");
+  const int64_t nl = int64_t(1) << L;
+  // outputs of forward stage s are the inputs of transposed step L - s; rows in T
+  std::vector<std::vector<std::vector<int64_t>>> off(bfs.size(), std::vector<std::vector<int64_t>>(size_t(L + 1)));
+  auto stage_rank = [&](const Butterfly &bf, int s, int64_t idx) {
+    return s == 0 ? bf.V0[size_t(idx)].m : bf.W[size_t(s)][size_t(idx)].m;
+  };
+  for (int s = L; s >= 0; --s)
+    for (size_t k = 0; k < bfs.size(); ++k) {
+      const int64_t cnt = nl;  // 2^s x 2^(L - s) blocks at every stage
+      off[k][size_t(s)].resize(size_t(cnt));
+      for (int64_t e = 0; e < cnt; ++e) {
+        off[k][size_t(s)][size_t(e)] = pk.t_rows;
+        pk.t_rows += stage_rank(*bfs[k], s, e);
+      }
+    }
+  // step 0: t(L, a) = B_a^T x(row leaf a), stacked by row leaf
+  {
+    const int64_t seg0 = int64_t(pk.segs.size());
+    std::map<int64_t, std::vector<std::pair<size_t, int64_t>>> byleaf;
+    for (size_t k = 0; k < bfs.size(); ++k)
+      for (int64_t a = 0; a < nl; ++a)
+        if (bfs[k]->B[size_t(a)].n > 0) byleaf[(bfs[k]->oi << L) + a].push_back({k, a});
+    std::vector<Mat> keep;
+    for (auto &[g, mem] : byleaf) {
+      std::vector<Member> ms;
+      keep.clear();
+      keep.reserve(mem.size());
+      for (auto [k, a] : mem) keep.push_back(transposed(bfs[k]->B[size_t(a)]));
+      for (size_t q = 0; q < mem.size(); ++q)
+        ms.push_back({&keep[q], off[mem[q].first][size_t(L)][size_t(mem[q].second)], 3, {0, 0, 0, 0}, L,
+                      mem[q].second, 0});
+      emit_group(pk, ms, 0, t.node_lo(ll, g), t.node_hi(ll, g) - t.node_lo(ll, g));
+    }
+    const int64_t ns = int64_t(pk.segs.size()) - seg0;
+    if (ns > 0) pk.launches.push_back({seg0, ns, 0, 0});
+  }
+  // steps for s = L .. 1: t(s-1, (ap, 2b)) ++ t(s-1, (ap, 2b+1)) = sum_c W_{2ap+c, b}^T t(s, .)
+  for (int s = L; s >= 1; --s) {
+    const int64_t seg0 = int64_t(pk.segs.size());
+    const int64_t nb = int64_t(1) << (L - s);
+    for (size_t k = 0; k < bfs.size(); ++k) {
+      const Butterfly &bf = *bfs[k];
+      for (int64_t ap = 0; ap < (int64_t(1) << (s - 1)); ++ap)
+        for (int64_t b = 0; b < nb; ++b) {
+          const int64_t e0 = ap * 2 * nb + 2 * b;
+          const int64_t rows = stage_rank(bf, s - 1, e0) + stage_rank(bf, s - 1, e0 + 1);
+          if (rows == 0) continue;
+          std::vector<Pair> prs;
+          for (int c = 0; c < 2; ++c) {
+            const int64_t e = (2 * ap + c) * nb + b;
+            const Mat &W = bf.W[size_t(s)][size_t(e)];
+            if (W.m == 0 || W.n == 0) continue;
+            if (W.n != rows) fail(HODBF_E_ARG, "inconsistent transfer block");
+            Pair p{};
+            p.scale = 1.0f;
+            p.f_off = pk.put_host(transposed(W), &p.scale);
+            p.in_buf = 1;
+            p.in_row = int32_t(off[k][size_t(s)][size_t(e)]);
+            p.n = W.m;
+            p.lda = int32_t(rows);
+            prs.push_back(p);
+          }
+          emit_sum(pk, prs, off[k][size_t(s - 1)][size_t(e0)], rows);
+        }
+    }
+    const int64_t ns = int64_t(pk.segs.size()) - seg0;
+    if (ns > 0) pk.launches.push_back({seg0, ns, 0, 0});
+  }
+  // last step: y(column leaf) = sum over butterflies of V0_b^T t(0, b)
+  {
+    const int64_t seg0 = int64_t(pk.segs.size());
+    std::map<int64_t, std::vector<std::pair<size_t, int64_t>>> byleaf;
+    for (size_t k = 0; k < bfs.size(); ++k)
+      for (int64_t b = 0; b < nl; ++b)
+        if (bfs[k]->V0[size_t(b)].m > 0) byleaf[(bfs[k]->si << L) + b].push_back({k, b});
+    for (auto &[g, mem] : byleaf) {
+      const int32_t lo = t.node_lo(ll, g), hi = t.node_hi(ll, g);
+      std::vector<Pair> prs;
+      for (auto [k, b] : mem) {
+        const Mat &V = bfs[k]->V0[size_t(b)];
+        Pair p{};
+        p.scale = 1.0f;
+        p.f_off = pk.put_host(transposed(V), &p.scale);
+        p.in_buf = 1;
+        p.in_row = int32_t(off[k][0][size_t(b)]);
+        p.n = V.m;
+        p.lda = hi - lo;
+        prs.push_back(p);
+      }
+      emit_sum(pk, prs, lo, hi - lo);
+    }
+    const int64_t ns = int64_t(pk.segs.size()) - seg0;
+    if (ns > 0) pk.launches.push_back({seg0, ns, 0, 1});
+  }
+}
+
+void check_program(const PackSink &pk, int64_t n_x, int64_t arena_count) {
+  for (const Launch &ln : pk.launches) {
+    const int64_t out_rows = ln.out ? n_x : pk.t_rows;
+    for (int64_t s = ln.s0; s < ln.s0 + ln.ns; ++s) {
+      const Seg &sg = pk.segs[size_t(s)];
+      if (sg.m < 0 || sg.m > kTileRows || sg.p0 < 0 || sg.p1 < sg.p0 ||
+          sg.p1 > int32_t(pk.pairs.size()) || sg.map0 < 0 || sg.map1 <= sg.map0 ||
+          sg.map1 - sg.map0 > kMaxMapEntries || sg.map1 > int32_t(pk.rowmap.size()))
+        fail(HODBF_E_ARG, "program check: malformed tile");
+      for (int32_t p = sg.p0; p < sg.p1; ++p) {
+        const Pair &pr = pk.pairs[size_t(p)];
+        const int64_t in_rows = pr.in_buf ? pk.t_rows : n_x;
+        if (pr.n < 0 || pr.in_row < 0 || int64_t(pr.in_row) + pr.n > in_rows)
+          fail(HODBF_E_ARG, "program check: input rows out of range");
+        if (pr.n > 0 && (pr.lda < sg.m || pr.f_off < 0 ||
+                         (arena_count >= 0 && pr.f_off + int64_t(pr.n - 1) * pr.lda + sg.m > arena_count)))
+          fail(HODBF_E_ARG, "program check: factor block out of range");
+      }
+      for (int32_t e = sg.map0; e < sg.map1; ++e) {
+        const RowMap &rm = pk.rowmap[size_t(e)];
+        const int32_t end = e + 1 < sg.map1 ? pk.rowmap[size_t(e + 1)].start : sg.m;
+        if (rm.start < 0 || end < rm.start || end > sg.m || (e == sg.map0 && rm.start != 0) ||
+            rm.out_row < 0 || int64_t(rm.out_row) + (end - rm.start) > out_rows)
+          fail(HODBF_E_ARG, "program check: output rows out of range");
+      }
+    }
+  }
+}
+
+void upload_program(Program &prog, PackSink &pk, hipStream_t st, bool log, int64_t n_x,
+                    int64_t arena_count) {
   retile(pk, kRetileBelow, kTileRows / 2);
+  if (n_x >= 0) check_program(pk, n_x, arena_count);
   for (Seg &sg : pk.segs)
     if (sg.p1 > sg.p0) sg.first = pk.pairs[size_t(sg.p0)];
   prog.io_rows = 0;
@@ -308,7 +501,7 @@ void upload_program(Program &prog, PackSink &pk, hipStream_t st) {
       ln.cls[c] = std::lower_bound(b, e, c + 1, [&](const Seg &sg, int v) { return nrt(sg) < v; }) - b;
   }
   // per-launch shape summary (tiles, rows, chunks of 16 columns per tile) for the log
-  for (size_t li = 0; li < pk.launches.size(); ++li) {
+  for (size_t li = 0; log && li < pk.launches.size(); ++li) {
     const Launch &ln = pk.launches[li];
     int64_t rows = 0, chunks = 0, cmax = 0;
     for (int64_t s = ln.s0; s < ln.s0 + ln.ns; ++s) {

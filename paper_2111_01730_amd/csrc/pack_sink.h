@@ -26,7 +26,17 @@ struct PackSink {
 void pack_group(PackSink &pk, const Tree &t, const std::vector<const Butterfly *> &bfs,
                 bool forward, int final_beta,
                 const std::function<void(const Butterfly &, int64_t *)> &meta);
-void upload_program(Program &prog, PackSink &pk, hipStream_t st);
+// y = M^T x for a set of butterflies of one shape (the stages reversed, factors
+// transposed; the last launch writes y's column-leaf rows with beta 0).
+void pack_group_t(PackSink &pk, const Tree &t, const std::vector<const Butterfly *> &bfs);
+// n_x >= 0: run check_program (below) on the final tiles first
+void upload_program(Program &prog, PackSink &pk, hipStream_t st, bool log = true,
+                    int64_t n_x = -1, int64_t arena_count = -1);
+// Host check of a packed program before it can reach a kernel: every tile's pairs read
+// inside their input buffer (X: n_x rows, T: t_rows) and inside the factor arena
+// (arena_count complex values; < 0 skips), and its row map writes inside the output.
+// E_ARG on the first violation.
+void check_program(const PackSink &pk, int64_t n_x, int64_t arena_count);
 // Launches with fewer tiles than this get half-height tiles at upload (more workgroups).
 // 512: with six waves per SIMD the split-BF16 kernel is 5-9% faster than with 1024 at
 // 1-64 right-hand sides (the FP32 kernel is indifferent), and no faster with 0-384.

@@ -14,7 +14,8 @@ namespace hodbf {
 // Butterflies of tree level l + 1 of the forward plan (the blocks Z(tau1, tau2) and
 // Z(tau2, tau1) of every level-l node), outer factors B^L filled from the kernel
 // entries; ca / cb / tau set to the children and their parent.
-std::vector<Butterfly> forward_offdiag_explicit(const FwdPlan &fp, const Kernel &ker, int l);
+std::vector<Butterfly> forward_offdiag_explicit(const Tree &t, const std::vector<Butterfly> &plan,
+                                               const Kernel &ker, int l);
 
 // Block table (rows of BlockRec) and values of a host-built preconditioner: leaf
 // inverses as kind 0 at level L_H, every X_tau butterfly's V^0 / W / B blocks with

@@ -10,11 +10,11 @@
 
 namespace hodbf {
 
-std::vector<Butterfly> forward_offdiag_explicit(const FwdPlan &fp, const Kernel &ker, int l) {
-  const Tree &t = fp.tree;
+std::vector<Butterfly> forward_offdiag_explicit(const Tree &t, const std::vector<Butterfly> &plan,
+                                               const Kernel &ker, int l) {
   const int LH = t.depth;
   std::vector<Butterfly> out;
-  for (const Butterfly &src : fp.bfs) {
+  for (const Butterfly &src : plan) {
     if (src.hod_level != l + 1) continue;
     Butterfly bf;
     bf.hod_level = src.hod_level;
@@ -31,14 +31,14 @@ std::vector<Butterfly> forward_offdiag_explicit(const FwdPlan &fp, const Kernel 
   // outer factors B^L = Z(tau_a, sbar_a) from the kernel entries
   std::vector<std::pair<size_t, int64_t>> jobs;
   size_t k = 0;
-  for (const Butterfly &src : fp.bfs) {
+  for (const Butterfly &src : plan) {
     if (src.hod_level != l + 1) continue;
     out[k].B.resize(size_t(int64_t(1) << src.L));
     for (int64_t a = 0; a < (int64_t(1) << src.L); ++a) jobs.push_back({k, a});
     ++k;
   }
   std::vector<const Butterfly *> srcs;
-  for (const Butterfly &src : fp.bfs)
+  for (const Butterfly &src : plan)
     if (src.hod_level == l + 1) srcs.push_back(&src);
 #pragma omp parallel for schedule(dynamic, 16)
   for (int64_t q = 0; q < int64_t(jobs.size()); ++q) {
@@ -122,7 +122,9 @@ extern "C" hodbf_status hodbf_precond_probe(const hodbf_build_params *params, in
     std::lock_guard<std::mutex> lk(g_pp_mu);
     const int64_t n = int64_t(params->nx) * params->ny * params->nz;
     if (n > 65536) fail(HODBF_E_ARG, "the host construction is for small problems (N <= 65536)");
-    std::vector<double> key = {double(params->nx), double(params->ny), double(params->nz),
+    const bool programs = which >= 16;
+    if (programs) which -= 16;
+    std::vector<double> key = {double(programs), double(params->nx), double(params->ny), double(params->nz),
                                params->h, params->k0, params->tol_con, params->tol_fact,
                                double(params->leaf_size), double(params->seed),
                                double(params->precond_min_level)};
@@ -131,13 +133,13 @@ extern "C" hodbf_status hodbf_precond_probe(const hodbf_build_params *params, in
       if (!(params->tol_fact > 0 && params->tol_fact < 1)) fail(HODBF_E_ARG, "tol_fact must lie in (0, 1)");
       FwdPlan fp = build_forward_plan(*params);
       fp.ker.tree = &fp.tree;
-      auto E = make_host_engine(&fp.tree, 256);
+      auto E = make_host_engine(&fp.tree, 256, programs);
       RbfOpts o;
       o.chi = params->tol_fact;
       o.seed = params->seed ^ 0xA5A5A5A5ull;
       const int minl = std::min(params->precond_min_level, fp.tree.depth);
       PrecondBuild pb = invert_hodbf(
-          *E, fp.ker, minl, [&](int l) { return forward_offdiag_explicit(fp, fp.ker, l); }, o);
+          *E, fp.ker, minl, [&](int l) { return forward_offdiag_explicit(fp.tree, fp.bfs, fp.ker, l); }, o);
       g_pp_perm = fp.tree.perm;
       export_precond_build(pb, fp.tree.depth, g_pp_table, g_pp_vals);
       g_pp_stats = {pb.reconstructions, pb.woodbury, pb.stats.sketch_cols, pb.stats.ids,

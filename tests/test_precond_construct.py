@@ -9,6 +9,9 @@ hodbf_precond_probe (complex FP64, no GPU) and checked against the oracle:
 * at chi_fact = 1e-2 and 1e-4 on a ragged grid: ||P Z x - x|| is of the size of the
   oracle's own (the same tolerance gives the same quality), and P differs from the
   oracle's P by O(chi_fact);
+* run through the device path's packed programs (forward and transposed, leaves above
+  the tree's for the recursion's coarser butterflies) by a host interpreter of their
+  descriptors, the same results;
 * the number of reconstructions is what the recursion of Algorithm 2 predicts (one for
   line 7 of Algorithm 1 per level, then per BF_SMW call: A22^{-1}, the Schur update
   and A11^{-1} recursively, and the final product)."""
@@ -22,13 +25,16 @@ from synth.workloads import small_case
 _lib = pytest.importorskip("paper_2111_01730_amd._lib")
 
 
-def _probe(g, chi_con, chi_fact, seed=1):
+def _probe(g, chi_con, chi_fact, seed=1, programs=False):
+    """programs: run every product through the device path's packed grouped-GEMM
+    programs (forward and transposed), interpreted on the host."""
     from tests.plan_tools import precond_from_export
     p = _lib.make_params(g, chi_con, chi_fact, precond_prec=1, seed=seed)
-    perm = _lib.probe(p, 0, np.int32, "hodbf_precond_probe")
-    tab = _lib.probe(p, 3, np.int64, "hodbf_precond_probe").reshape(-1, 12)
-    vals = _lib.probe(p, 4, np.complex128, "hodbf_precond_probe")
-    stats = _lib.probe(p, 7, np.int64, "hodbf_precond_probe")
+    o = 16 if programs else 0
+    perm = _lib.probe(p, 0 + o, np.int32, "hodbf_precond_probe")
+    tab = _lib.probe(p, 3 + o, np.int64, "hodbf_precond_probe").reshape(-1, 12)
+    vals = _lib.probe(p, 4 + o, np.complex128, "hodbf_precond_probe")
+    stats = _lib.probe(p, 7 + o, np.int64, "hodbf_precond_probe")
     depth = int(tab[tab[:, 0] == 0][0, 1])
     return precond_from_export(g, perm, tab, vals, depth), stats, depth
 
@@ -37,10 +43,11 @@ def _rel(a, b):
     return np.linalg.norm(a - b, axis=0) / np.linalg.norm(b, axis=0)
 
 
-def test_tight_tolerances_give_the_inverse():
+@pytest.mark.parametrize("programs", [False, True])
+def test_tight_tolerances_give_the_inverse(programs):
     c = small_case(61, sides=(8, 8, 8), h=0.1, eps_range=(2.0, 6.0), loss=0.3, nrhs=4)
     g = c["grid"]
-    P, stats, _ = _probe(g, 1e-10, 1e-10)
+    P, stats, _ = _probe(g, 1e-10, 1e-10, programs=programs)
     Z = vie.dense(g)
     x = c["x"]
     assert np.all(_rel(P.apply(Z @ x), x) <= 1e-6)  # FP32 storage of the factors
@@ -54,11 +61,11 @@ def ragged():
     return c, vie.dense(c["grid"])
 
 
-@pytest.mark.parametrize("chi_fact", [1e-2, 1e-4])
-def test_quality_matches_the_oracle(ragged, chi_fact):
+@pytest.mark.parametrize("chi_fact,programs", [(1e-2, False), (1e-4, False), (1e-2, True)])
+def test_quality_matches_the_oracle(ragged, chi_fact, programs):
     c, Z = ragged
     g = c["grid"]
-    P, _, _ = _probe(g, 1e-6, chi_fact)
+    P, _, _ = _probe(g, 1e-6, chi_fact, programs=programs)
     x = c["x"]
     po = oprecond.build_precond(g, chi_fact)
     mine = _rel(P.apply(Z @ x), x).max()
