@@ -153,7 +153,7 @@ def dense_case(case):
 
 # split arithmetic: 2^-15 against 2^-24 per product, as for the leaf form
 @pytest.mark.parametrize("which,tol", [(2, 2e-5), (6, 512 * 2e-5)])
-def test_dense_bottom_matches_exported_factors(dense_case, which, tol):
+def test_dense_bottom_matches_exported_factors(dense_case, case, which, tol):
     from tests.plan_tools import DenseBottomPrecond, precond_from_export
     c, g, op, Z = dense_case
     LH = op.stats()["levels"]
