@@ -43,7 +43,7 @@ typedef enum {
   HODBF_OK = 0,
   HODBF_E_ARG = -1,     /* invalid argument: shape, pointer, tolerance, eps */
   HODBF_E_NOMEM = -2,   /* device allocation failed or the HBM budget is exceeded */
-  HODBF_E_HIP = -3,     /* a HIP / rocBLAS / rocSOLVER call failed */
+  HODBF_E_HIP = -3,     /* a HIP call failed */
   HODBF_E_NUMERIC = -4, /* NaN or Inf met in a residual or a factorization */
   HODBF_E_NOCONV = -5,  /* vie_solve hit max_iter; x holds the last iterate */
   HODBF_E_STATE = -6    /* the operator lacks what the call needs (no preconditioner) */
@@ -83,12 +83,13 @@ typedef struct {
   int32_t leaf_size;     /* leaf cluster size of T_H, 1..64 (64 recommended) */
   int32_t precond_prec;  /* hodbf_prec bit mask, 0..7 */
   int32_t precond_min_level; /* levels < this get no X_tau (0 = full Algorithm 1 form) */
-  int32_t precond_dense_levels; /* d >= 0: the leaf inverses and the X_tau of the d lowest
-                                   tree levels are replaced by the exact dense inverses of
-                                   the diagonal blocks Z(tau, tau) of the level L_H - d
-                                   nodes (what those factors compose to, Algorithm 1, up to
-                                   chi_fact); 0 = leaves of the tree; E_ARG if L_H - d <
-                                   precond_min_level (clamped to L_H otherwise) */
+  int32_t precond_dense_levels; /* d >= 0: Algorithm 1's recursion starts from the dense
+                                   inverses of the diagonal blocks of the level L_H - d
+                                   nodes (computed directly, FP64 on the host, stored like
+                                   the other factors) instead of the leaves, so the d lowest
+                                   levels are exact and applied in one launch; 0 = leaves
+                                   of the tree; E_ARG if L_H - d < precond_min_level
+                                   (clamped to L_H otherwise) */
   uint64_t seed;         /* row-sampling RNG seed */
   size_t hbm_budget;     /* bytes of device memory the operator may hold; 0 = unlimited */
   void *stream;          /* hipStream_t used for construction */
@@ -98,7 +99,12 @@ typedef struct {
  * hodbf_build -- compress Z in HOD-BF form (Section III-A: cluster tree T_H, dense
  * leaf blocks D_tau, nested-ID butterflies for every off-diagonal sibling block) and,
  * if precond_prec != HODBF_P_NONE, its approximate inverse in the multiplicative
- * form of Algorithm 1 (Section III-B).  Blocks until the operator is ready.
+ * form of Algorithm 1 (Section III-B), built bottom-up on the device: D^{-1} B of each
+ * level and the BF_SMW steps of Algorithm 2 each reconstructed as butterflies from
+ * products with structured random vectors (BF_random_matvec), the blocks kept at
+ * tol_fact, intermediate ones at 1e-2 tol_fact (the environment variable
+ * HODBF_CHI_INNER, if set, overrides that tolerance).  Blocks until the operator is
+ * ready.
  * *out receives a new operator owned by the caller (release with hodbf_free).
  * Errors: E_ARG (bad grid, h, k0, tolerance, leaf size, eps = 0 or non-finite),
  * E_NOMEM (allocation or hbm_budget), E_HIP, E_NUMERIC (singular diagonal block).
@@ -243,9 +249,9 @@ const char *hodbf_last_error(void);
  * allocator's business (scratch is released after the call's last use was enqueued on
  * its stream).  Operator arenas remember the hook they were allocated with; per-call
  * workspace comes from the hook installed when the call starts and goes back to it,
- * also when the call fails; change the hook only while no call is running.  alloc == NULL restores hipMalloc / hipMallocAsync.  The dense
- * factorisations of the preconditioner construction keep their own rocSOLVER
- * temporaries.  E_ARG if alloc is set and release is not.  Process-wide, thread-safe.
+ * also when the call fails; change the hook only while no call is running.
+ * alloc == NULL restores hipMalloc / hipMallocAsync.  E_ARG if alloc is set and release
+ * is not.  Process-wide, thread-safe.
  */
 typedef void *(*hodbf_alloc_fn)(size_t bytes, void *stream, void *ctx);
 typedef void (*hodbf_free_fn)(void *ptr, void *ctx);

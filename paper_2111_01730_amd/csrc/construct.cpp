@@ -206,36 +206,63 @@ class SmwProduct final : public LinOp {
 // ---------------------------------------------------------------------------
 // small dense helpers (complex FP64, column-major)
 
-// In-place inverse by Gauss-Jordan elimination with partial pivoting.
+// In-place inverse by Gauss-Jordan elimination with partial pivoting (row interchanges,
+// undone as column interchanges in reverse order at the end).  Column-major; each
+// elimination step is a rank-1 update whose inner loop runs down a contiguous column,
+// written on the real and imaginary parts.
 void inverse_inplace(std::vector<cd> &A, int n) {
-  std::vector<cd> I(static_cast<size_t>(n) * n, cd(0, 0));
-  for (int i = 0; i < n; ++i) I[size_t(i) * n + i] = 1.0;
+  std::vector<int> piv(static_cast<size_t>(n));
+  std::vector<double> mc(2 * static_cast<size_t>(n));
+  double *a = reinterpret_cast<double *>(A.data());
   for (int c = 0; c < n; ++c) {
+    double *colc = a + 2 * size_t(c) * n;
     int p = c;
-    for (int r = c + 1; r < n; ++r)
-      if (std::abs(A[size_t(c) * n + r]) > std::abs(A[size_t(c) * n + p])) p = r;
-    if (!(std::abs(A[size_t(c) * n + p]) > 0)) fail(HODBF_E_NUMERIC, "singular block in the preconditioner");
+    double best = std::hypot(colc[2 * c], colc[2 * c + 1]);
+    for (int r = c + 1; r < n; ++r) {
+      const double v = std::hypot(colc[2 * r], colc[2 * r + 1]);
+      if (v > best) {
+        best = v;
+        p = r;
+      }
+    }
+    if (!(best > 0) || !std::isfinite(best)) fail(HODBF_E_NUMERIC, "singular block in the preconditioner");
+    piv[size_t(c)] = p;
     if (p != c)
       for (int k = 0; k < n; ++k) {
-        std::swap(A[size_t(k) * n + p], A[size_t(k) * n + c]);
-        std::swap(I[size_t(k) * n + p], I[size_t(k) * n + c]);
+        double *col = a + 2 * size_t(k) * n;
+        std::swap(col[2 * p], col[2 * c]);
+        std::swap(col[2 * p + 1], col[2 * c + 1]);
       }
-    const cd inv = 1.0 / A[size_t(c) * n + c];
+    // d = 1 / A(c, c); the old column c is kept as the multipliers
+    const double pr = colc[2 * c], pi = colc[2 * c + 1], den = pr * pr + pi * pi;
+    const double dr = pr / den, di = -pi / den;
+    std::copy(colc, colc + 2 * size_t(n), mc.data());
     for (int k = 0; k < n; ++k) {
-      A[size_t(k) * n + c] *= inv;
-      I[size_t(k) * n + c] *= inv;
+      if (k == c) continue;
+      double *col = a + 2 * size_t(k) * n;
+      const double fr = col[2 * c] * dr - col[2 * c + 1] * di;
+      const double fi = col[2 * c] * di + col[2 * c + 1] * dr;
+      if (fr != 0 || fi != 0)
+        for (int r = 0; r < n; ++r) {
+          col[2 * r] -= mc[2 * size_t(r)] * fr - mc[2 * size_t(r) + 1] * fi;
+          col[2 * r + 1] -= mc[2 * size_t(r)] * fi + mc[2 * size_t(r) + 1] * fr;
+        }
+      col[2 * c] = fr;
+      col[2 * c + 1] = fi;
     }
     for (int r = 0; r < n; ++r) {
-      if (r == c) continue;
-      const cd f = A[size_t(c) * n + r];
-      if (f == cd(0, 0)) continue;
-      for (int k = 0; k < n; ++k) {
-        A[size_t(k) * n + r] -= f * A[size_t(k) * n + c];
-        I[size_t(k) * n + r] -= f * I[size_t(k) * n + c];
-      }
+      const double mr = mc[2 * size_t(r)], mi = mc[2 * size_t(r) + 1];
+      colc[2 * r] = -(mr * dr - mi * di);
+      colc[2 * r + 1] = -(mr * di + mi * dr);
     }
+    colc[2 * c] = dr;
+    colc[2 * c + 1] = di;
   }
-  A.swap(I);
+  for (int c = n - 1; c >= 0; --c) {
+    const int p = piv[size_t(c)];
+    if (p != c)
+      std::swap_ranges(a + 2 * size_t(c) * n, a + 2 * size_t(c + 1) * n, a + 2 * size_t(p) * n);
+  }
 }
 
 // X (n x nrhs) minimizing ||A X - B||_F, A m x n, B m x nrhs (column-major), by
@@ -471,7 +498,7 @@ std::vector<Butterfly> reconstruct(Engine &E, const LinOp &M, int lev, int L,
   }
   const uint64_t seed0 = mix(mix(o.seed, uint64_t(lev)), uint64_t(L) + 1000 * uint64_t(T));
   std::vector<SideLevel> C(static_cast<size_t>(h + 1)), Rw(size_t(L - h + 1));
-  int k_cur[2] = {o.k0, o.k0};
+  int k_cur[2] = {o.k0_side[0] > 0 ? o.k0_side[0] : o.k0, o.k0_side[1] > 0 ? o.k0_side[1] : o.k0};
 
   // one sweep level of one side: sketch, gather the candidates of every pair, ID them
   auto sweep = [&](bool colside, int j, int kmin) {
@@ -597,10 +624,11 @@ std::vector<Butterfly> reconstruct(Engine &E, const LinOp &M, int lev, int L,
       }
       if (st) {
         st->ids += int64_t(T) * npair;
-        st->seconds_host += seconds_since(th);
+        st->seconds_id += seconds_since(th);
         st->max_rank = std::max(st->max_rank, maxr);
       }
       if (saturated && k < o.kmax) {
+        if (st) ++st->redone;
         logf("    sketch width %d saturated (%d blocks, rank %d) at %s level %d; doubling", k,
              saturated, maxr, colside ? "column" : "row", j);
         k = std::min(2 * k, o.kmax);
@@ -619,6 +647,10 @@ std::vector<Butterfly> reconstruct(Engine &E, const LinOp &M, int lev, int L,
   for (const auto &tb : C[size_t(h)].skel)
     for (const auto &s : tb) max_rc = std::max(max_rc, int(s.size()));
   for (int j = 0; j <= L - h; ++j) sweep(false, j, j == L - h ? max_rc + o.oversample : 0);
+  if (st) {
+    st->last_k[0] = k_cur[0];
+    st->last_k[1] = k_cur[1];
+  }
 
   // middle: S_{tau,nu} (r_r x r_c) with X_nu(rows tau_bar, :) ~ S (V_{tau,nu} Omega_nu),
   // V_{tau,nu} Omega_nu propagated through the column-side factors on the host
@@ -691,7 +723,7 @@ std::vector<Butterfly> reconstruct(Engine &E, const LinOp &M, int lev, int L,
         for (int c = 0; c < rc; ++c) Sm.v[size_t(c) * rr + i] = cf(St[size_t(i) * rc + c]);
     }
   }
-  if (st) st->seconds_host += seconds_since(tm);
+  if (st) st->seconds_middle += seconds_since(tm);
 
   // assemble
   std::vector<Butterfly> out(static_cast<size_t>(T));
@@ -777,8 +809,11 @@ namespace {
 
 struct Ctx {
   Engine &E;
-  const RbfOpts &o;
+  RbfOpts o;  // tolerances of the level being built
   PrecondBuild &pb;
+  // final sketch widths of earlier reconstructions of the same shape and role: the next
+  // one starts there instead of doubling up from k0 again
+  std::map<std::tuple<int, int, int>, std::pair<int, int>> khint;
 };
 
 RowSet rows_of(const Tree &t, int lev, const std::vector<int64_t> &nodes) {
@@ -787,24 +822,43 @@ RowSet rows_of(const Tree &t, int lev, const std::vector<int64_t> &nodes) {
   return r;
 }
 
-std::vector<Butterfly> rbf(Ctx &c, const LinOp &M, int lev, int L, const std::vector<Target> &tg) {
+// final: the X_tau blocks a level keeps (tolerance chi); every intermediate operator of
+// Algorithms 1-2 (D^{-1} B, the Schur update, the split and low-rank blocks) is
+// reconstructed at chi_inner, since the inverses taken of them amplify its error
+std::vector<Butterfly> rbf(Ctx &c, const LinOp &M, int lev, int L, const std::vector<Target> &tg,
+                           int role, bool final = false) {
   ++c.pb.reconstructions;
   auto t0 = std::chrono::steady_clock::now();
   RbfOpts oo = c.o;
+  if (!final && c.o.chi_inner > 0) oo.chi = c.o.chi_inner;
+  const auto key = std::make_tuple(L, role, final ? 1 : 0);
+  auto hit = c.khint.find(key);
+  if (hit != c.khint.end()) {
+    oo.k0_side[0] = hit->second.first;
+    oo.k0_side[1] = hit->second.second;
+  }
   oo.seed = mix(c.o.seed, uint64_t(c.pb.reconstructions));
   auto out = reconstruct(c.E, M, lev, L, tg, oo, &c.pb.stats);
+  c.khint[key] = {c.pb.stats.last_k[0], c.pb.stats.last_k[1]};
   if (tg.size() && L >= 6)
     logf("    reconstructed %zu butterflies at level %d (%d levels) in %.2f s", tg.size(), lev, L,
          seconds_since(t0));
   return out;
 }
 
-OpP subset_op(Engine &E, const std::vector<Butterfly> &bfs, int ca, int cb) {
+OpP packed(Ctx &c, std::vector<Butterfly> bfs) {
+  auto t0 = std::chrono::steady_clock::now();
+  OpP op = c.E.butterflies(std::move(bfs));
+  c.pb.stats.seconds_pack += seconds_since(t0);
+  return op;
+}
+
+OpP subset_op(Ctx &c, const std::vector<Butterfly> &bfs, int ca, int cb) {
   std::vector<Butterfly> s;
   for (const auto &bf : bfs)
     if (bf.ca == ca && bf.cb == cb) s.push_back(bf);
   if (s.empty()) return nullptr;
-  return E.butterflies(std::move(s));
+  return packed(c, std::move(s));
 }
 
 std::vector<Target> children_targets(const std::vector<int64_t> &nodes) {
@@ -816,7 +870,7 @@ std::vector<Target> children_targets(const std::vector<int64_t> &nodes) {
 }
 
 std::vector<Butterfly> smw(Ctx &c, const std::vector<int64_t> &nodes, int lev, int Lc, OpP E11,
-                           OpP E12, OpP E21, OpP E22);
+                           OpP E12, OpP E21, OpP E22, bool top = false);
 
 // (I + E)^{-1} - I on the diagonal blocks (v, v) of the nodes, E given as an operator on
 // those blocks whose butterfly form has Lc levels.  Splits E into its four children
@@ -828,7 +882,7 @@ OpP inv_minus_identity(Ctx &c, const std::vector<int64_t> &nodes, int lev, int L
   if (Lc - 2 < 0 || lev + 1 > t.depth) {
     std::vector<Target> tg;
     for (int64_t v : nodes) tg.push_back({v, v, 0, 0, v / 2});
-    std::vector<Butterfly> lr = rbf(c, *E, lev, 0, tg);
+    std::vector<Butterfly> lr = rbf(c, *E, lev, 0, tg, 1);
     for (Butterfly &bf : lr) {
       // E ~ B V: (I + B V)^{-1} - I = -B (I + V B)^{-1} V
       Mat &V = bf.V0[0];
@@ -849,21 +903,21 @@ OpP inv_minus_identity(Ctx &c, const std::vector<int64_t> &nodes, int lev, int L
       B = to_mat(nb, B.m, r);
       ++c.pb.woodbury;
     }
-    return c.E.butterflies(std::move(lr));
+    return packed(c, std::move(lr));
   }
-  std::vector<Butterfly> kids = rbf(c, *E, lev + 1, Lc - 2, children_targets(nodes));
-  OpP C11 = subset_op(c.E, kids, 0, 0), C12 = subset_op(c.E, kids, 0, 1);
-  OpP C21 = subset_op(c.E, kids, 1, 0), C22 = subset_op(c.E, kids, 1, 1);
+  std::vector<Butterfly> kids = rbf(c, *E, lev + 1, Lc - 2, children_targets(nodes), 2);
+  OpP C11 = subset_op(c, kids, 0, 0), C12 = subset_op(c, kids, 0, 1);
+  OpP C21 = subset_op(c, kids, 1, 0), C22 = subset_op(c, kids, 1, 1);
   kids.clear();
   std::vector<Butterfly> F = smw(c, nodes, lev, Lc - 2, C11, C12, C21, C22);
-  return c.E.butterflies(std::move(F));
+  return packed(c, std::move(F));
 }
 
 // Algorithm 2 on A = I + E for every node of `nodes` (level lev), E given by its four
 // child blocks (operators on (child i, child j), Lc butterfly levels each; nullptr = 0).
 // Returns A^{-1} - I as four child butterflies per node with Lc levels.
 std::vector<Butterfly> smw(Ctx &c, const std::vector<int64_t> &nodes, int lev, int Lc, OpP E11,
-                           OpP E12, OpP E21, OpP E22) {
+                           OpP E12, OpP E21, OpP E22, bool top) {
   const Tree &t = *c.E.tree;
   std::vector<int64_t> n1, n2;
   for (int64_t v : nodes) {
@@ -885,25 +939,28 @@ std::vector<Butterfly> smw(Ctx &c, const std::vector<int64_t> &nodes, int lev, i
   OpP F11 = inv_minus_identity(c, n1, lev + 1, Lc, E11p);
   // line 5: A^{-1} - I as the product, reconstructed into four child butterflies
   SmwProduct prod(E12, E21, F11, F22, rows_of(t, lev + 1, n1), rows_of(t, lev + 1, n2));
-  return rbf(c, prod, lev + 1, Lc, children_targets(nodes));
+  return rbf(c, prod, lev + 1, Lc, children_targets(nodes), 3, top);
 }
 
 }  // namespace
 
-PrecondBuild invert_hodbf(Engine &E, const Kernel &ker, int min_level,
+PrecondBuild invert_hodbf(Engine &E, const Kernel &ker, int min_level, int leaf_level,
                           const std::function<std::vector<Butterfly>(int)> &fwd_offdiag,
                           const RbfOpts &o) {
   const Tree &t = *E.tree;
   const int LH = t.depth;
+  if (leaf_level < min_level || leaf_level > LH) fail(HODBF_E_ARG, "inverse leaf level out of range");
   PrecondBuild pb;
+  pb.leaf_level = leaf_level;
   Ctx c{E, o, pb};
   auto t0 = std::chrono::steady_clock::now();
-  // line 3 at the leaves: dense inverses
-  const int64_t nleaf = int64_t(1) << LH;
+  // line 3 at the leaves of the recursion (the nodes of leaf_level): dense inverses of
+  // the diagonal blocks from the kernel's entries
+  const int64_t nleaf = int64_t(1) << leaf_level;
   pb.leaf_inv.resize(size_t(nleaf));
-#pragma omp parallel for schedule(dynamic, 8)
+#pragma omp parallel for schedule(dynamic, 1)
   for (int64_t g = 0; g < nleaf; ++g) {
-    const int32_t lo = t.node_lo(LH, g), hi = t.node_hi(LH, g);
+    const int32_t lo = t.node_lo(leaf_level, g), hi = t.node_hi(leaf_level, g);
     const int m = hi - lo;
     std::vector<cd> D(static_cast<size_t>(m) * m);
     for (int cc = 0; cc < m; ++cc)
@@ -915,13 +972,20 @@ PrecondBuild invert_hodbf(Engine &E, const Kernel &ker, int min_level,
   OpP leaf = E.dense_diag(pb.leaf_inv);
   pb.leaf_op = leaf;
   std::vector<OpP> built;
-  for (int l = LH - 1; l >= min_level; --l) {
+  logf("preconditioner: %lld dense inverses at level %d, %.2f s", (long long)nleaf, leaf_level,
+       seconds_since(t0));
+  for (int l = leaf_level - 1; l >= min_level; --l) {
     auto tl = std::chrono::steady_clock::now();
+    // tolerances of this level: chi_fact / decay^l (an error made at level l reaches the
+    // root through the l levels above it, each multiplying it by about ||A_tau^{-1}||)
+    const double lf = std::pow(o.chi_decay, -double(l));
+    c.o.chi = o.chi * lf;
+    c.o.chi_inner = o.chi_inner * lf;
     const int Lb = LH - l - 1;
     std::vector<int64_t> nodes(static_cast<size_t>(int64_t(1) << l));
     for (size_t i = 0; i < nodes.size(); ++i) nodes[i] = int64_t(i);
     // line 7: B_tau_i <- D_tau_i^{-1} B_tau_i for both children of every node
-    OpP O = E.butterflies(fwd_offdiag(l));
+    OpP O = packed(c, fwd_offdiag(l));
     OpP Dinv = mult_inverse(E, leaf, built);
     OpP M7 = chain({O, Dinv});
     std::vector<Target> tg;
@@ -929,19 +993,22 @@ PrecondBuild invert_hodbf(Engine &E, const Kernel &ker, int min_level,
       tg.push_back({2 * v, 2 * v + 1, 0, 1, v});
       tg.push_back({2 * v + 1, 2 * v, 1, 0, v});
     }
-    std::vector<Butterfly> Bp = rbf(c, *M7, l + 1, Lb, tg);
+    std::vector<Butterfly> Bp = rbf(c, *M7, l + 1, Lb, tg, 0);
     O.reset();
     M7.reset();
-    OpP E12 = subset_op(E, Bp, 0, 1), E21 = subset_op(E, Bp, 1, 0);
+    OpP E12 = subset_op(c, Bp, 0, 1), E21 = subset_op(c, Bp, 1, 0);
     Bp.clear();
     // line 8: D_tau^{-1} = BF_SMW([I, B1; B2, I]) diag(D1^{-1}, D2^{-1})
-    std::vector<Butterfly> X = smw(c, nodes, l, Lb, nullptr, E12, E21, nullptr);
-    built.push_back(E.butterflies(X));
+    std::vector<Butterfly> X = smw(c, nodes, l, Lb, nullptr, E12, E21, nullptr, true);
+    built.push_back(packed(c, X));
     pb.levels.push_back(std::move(X));
     pb.ops.push_back(built.back());
     logf("preconditioner level %d: %lld nodes, %.2f s (%.2f s so far), %lld reconstructions, "
-         "%lld sketch columns", l, (long long)nodes.size(), seconds_since(tl), seconds_since(t0),
-         (long long)pb.reconstructions, (long long)pb.stats.sketch_cols);
+         "%lld sketch columns (%lld redone levels), largest rank %d; seconds so far: products "
+         "%.1f, IDs %.1f, middle %.1f, packing %.1f", l, (long long)nodes.size(), seconds_since(tl),
+         seconds_since(t0), (long long)pb.reconstructions, (long long)pb.stats.sketch_cols,
+         (long long)pb.stats.redone, pb.stats.max_rank, pb.stats.seconds_apply, pb.stats.seconds_id,
+         pb.stats.seconds_middle, pb.stats.seconds_pack);
   }
   return pb;
 }

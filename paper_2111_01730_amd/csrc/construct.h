@@ -108,8 +108,11 @@ struct Target {
 
 struct RbfOpts {
   double chi = 1e-4;
+  double chi_inner = 0;  // tolerance of intermediate reconstructions (0: chi)
+  double chi_decay = 1;  // level l of Algorithm 1 runs at chi / chi_decay^l (and chi_inner)
   uint64_t seed = 1;
   int k0 = 32;        // first sketch width per slot
+  int k0_side[2] = {0, 0};  // first widths of the column and row sides (0: k0)
   int oversample = 10;
   int kmax = 4096;
   // the operator is nonzero only on the target blocks (true for every use here): the
@@ -118,9 +121,12 @@ struct RbfOpts {
 };
 
 struct RbfStats {
-  int64_t sketch_cols = 0, ids = 0, applies = 0;
+  int64_t sketch_cols = 0, ids = 0, applies = 0, redone = 0;
   int max_rank = 0;
-  double seconds_apply = 0, seconds_host = 0;
+  int last_k[2] = {0, 0};  // final sketch widths of the last reconstruction (column, row side)
+  // sketch products (incl. gathers), interpolative decompositions, middle fit, and
+  // the engine's packing of new butterfly sets
+  double seconds_apply = 0, seconds_id = 0, seconds_middle = 0, seconds_pack = 0;
 };
 
 // Reconstruct the target butterflies of M (two-sided nested form: column IDs of
@@ -134,18 +140,21 @@ std::vector<Butterfly> reconstruct(Engine &E, const LinOp &M, int lev, int L,
 
 // Algorithm 1 driver.  fwd_offdiag(l) returns the forward operator's butterflies of
 // tree level l + 1 (the blocks Z(tau1, tau2), Z(tau2, tau1) of every level-l node) with
-// explicit outer factors.  Leaves: dense inverses (host FP64).  Returns, per tree level
-// from L_H - 1 down to min_level, the X_tau butterflies (four per node, children pairs,
-// L_H - l - 1 levels), and the leaf inverses.
+// explicit outer factors.  The recursion bottoms out at the nodes of leaf_level (L_H:
+// the tree's leaves; higher: larger nodes), whose diagonal blocks are inverted densely
+// (host FP64).  Returns, per tree level from leaf_level - 1 down to min_level, the X_tau
+// butterflies (four per node, children pairs, L_H - l - 1 levels), and the dense
+// inverses.
 struct PrecondBuild {
   std::vector<DenseDiag> leaf_inv;
-  std::vector<std::vector<Butterfly>> levels;  // levels[i] is tree level L_H - 1 - i
+  int leaf_level = 0;
+  std::vector<std::vector<Butterfly>> levels;  // levels[i] is tree level leaf_level - 1 - i
   OpP leaf_op;              // the leaf inverses as the engine's operator
   std::vector<OpP> ops;     // X of each built level as the engine's operator (same order)
   RbfStats stats;
   int64_t reconstructions = 0, woodbury = 0;
 };
-PrecondBuild invert_hodbf(Engine &E, const Kernel &ker, int min_level,
+PrecondBuild invert_hodbf(Engine &E, const Kernel &ker, int min_level, int leaf_level,
                           const std::function<std::vector<Butterfly>(int)> &fwd_offdiag,
                           const RbfOpts &o);
 

@@ -1,7 +1,8 @@
-// Device engine of the preconditioner construction: multi-vectors in complex FP32 on
+// Device engine of the preconditioner construction: multi-vectors in complex FP64 on
 // the GPU, butterfly sets and dense diagonal blocks packed into grouped-GEMM programs
-// (one forward, one transposed) with their own FP32 arena; elementwise work, sketch
-// generation and row gathers by the kernels of construct.hip.  One stream throughout.
+// (one forward, one transposed) over their own FP32 arena and run in FP64; elementwise
+// work, sketch generation and row gathers by the kernels of construct.hip.  One stream
+// throughout.
 #include <map>
 
 #include "construct.h"
@@ -17,7 +18,7 @@ class DevEngine;
 struct DevMv final : Mv {
   DevEngine *eng = nullptr;
   DevBuf buf;
-  float2 *p() const { return buf.as<float2>(); }
+  double2 *p() const { return buf.as<double2>(); }
   ~DevMv() override;
 };
 
@@ -34,7 +35,7 @@ class DevEngine final : public Engine {
     auto m = std::make_shared<DevMv>();
     m->R = R;
     m->eng = this;
-    const size_t bytes = size_t(n()) * size_t(R) * sizeof(float2);
+    const size_t bytes = size_t(n()) * size_t(R) * sizeof(double2);
     auto it = pool_.find(bytes);
     if (it != pool_.end()) {
       m->buf = std::move(it->second);
@@ -42,7 +43,8 @@ class DevEngine final : public Engine {
     } else {
       m->buf.alloc(bytes);
     }
-    if (bytes) HIPCHK(hipMemsetAsync(m->buf.p, 0, bytes, st_));
+    // not cleared: every multi-vector of the construction is written whole by its
+    // producer (a fill, a copy or an operator apply) before it is read
     return m;
   }
   void recycle(DevBuf &&b) {
@@ -58,26 +60,34 @@ class DevEngine final : public Engine {
   }
   void axpy(cd a, const Mv &x, Mv &y) override {
     if (x.R != y.R) fail(HODBF_E_ARG, "multi-vector widths differ");
-    launch_axpy_c64(dv(y).p(), dv(x).p(), float(a.real()), float(a.imag()), n() * x.R, st_);
+    launch_axpy_c128(dv(y).p(), dv(x).p(), a.real(), a.imag(), n() * x.R, st_);
     HIPCHK(hipGetLastError());
   }
   void keep_rows(const RowSet &rows, Mv &y) override {
-    std::vector<uint8_t> keep(size_t(n()), 0);
-    for (auto [lo, hi] : rows)
-      for (int32_t r = lo; r < hi; ++r) keep[size_t(r)] = 1;
-    flags_.upload(keep.data(), keep.size(), st_);
-    launch_keep_rows(dv(y).p(), flags_.as<uint8_t>(), n(), y.R, st_);
+    // row masks recur (the same child row sets in every product of one recursion step):
+    // kept on the device, keyed by their ranges
+    auto it = masks_.find(rows);
+    if (it == masks_.end()) {
+      if (masks_.size() > 64) masks_.clear();
+      std::vector<uint8_t> keep(size_t(n()), 0);
+      for (auto [lo, hi] : rows)
+        for (int32_t r = lo; r < hi; ++r) keep[size_t(r)] = 1;
+      DevBuf b;
+      b.upload(keep.data(), keep.size(), st_);
+      it = masks_.emplace(rows, std::move(b)).first;
+    }
+    launch_keep_rows_c128(dv(y).p(), it->second.as<uint8_t>(), n(), y.R, st_);
     HIPCHK(hipGetLastError());
   }
   void fill_sketch(Mv &x, const std::vector<int32_t> &slot_of_row, int64_t col0, int k,
                    uint64_t seed) override {
-    slots_.upload(slot_of_row.data(), slot_of_row.size() * sizeof(int32_t), st_);
-    launch_fill_sketch(dv(x).p(), slots_.as<int32_t>(), n(), x.R, col0, k, seed, st_);
+    stage(slots_, slot_of_row.data(), slot_of_row.size() * sizeof(int32_t));
+    launch_fill_sketch_c128(dv(x).p(), slots_.as<int32_t>(), n(), x.R, col0, k, seed, st_);
     HIPCHK(hipGetLastError());
   }
   void fill_unit(Mv &x, const std::vector<int32_t> &col_of_row) override {
-    slots_.upload(col_of_row.data(), col_of_row.size() * sizeof(int32_t), st_);
-    launch_fill_unit(dv(x).p(), slots_.as<int32_t>(), n(), x.R, st_);
+    stage(slots_, col_of_row.data(), col_of_row.size() * sizeof(int32_t));
+    launch_fill_unit_c128(dv(x).p(), slots_.as<int32_t>(), n(), x.R, st_);
     HIPCHK(hipGetLastError());
   }
   void gather(const Mv &y, const std::vector<Gather> &req, int k, std::vector<cd> &out) override {
@@ -90,15 +100,14 @@ class DevEngine final : public Engine {
       }
     out.assign(rows.size() * size_t(k), cd(0, 0));
     if (rows.empty()) return;
-    DevBuf dr, dq, dout;
-    dr.upload(rows.data(), rows.size() * sizeof(int32_t), st_);
-    dq.upload(q0.data(), q0.size() * sizeof(int32_t), st_);
-    dout.alloc(rows.size() * size_t(k) * sizeof(float2));
-    launch_gather_rows(dv(y).p(), y.R, dr.as<int32_t>(), dq.as<int32_t>(), int64_t(rows.size()), k,
-                       dout.as<float2>(), st_);
+    stage(grows_, rows.data(), rows.size() * sizeof(int32_t));
+    stage(gq0_, q0.data(), q0.size() * sizeof(int32_t));
+    grow(gout_, rows.size() * size_t(k) * sizeof(double2));
+    launch_gather_rows_c128(dv(y).p(), y.R, grows_.as<int32_t>(), gq0_.as<int32_t>(),
+                            int64_t(rows.size()), k, gout_.as<double2>(), st_);
     HIPCHK(hipGetLastError());
-    std::vector<float2> h(rows.size() * size_t(k));
-    HIPCHK(hipMemcpyAsync(h.data(), dout.p, h.size() * sizeof(float2), hipMemcpyDeviceToHost, st_));
+    std::vector<double2> h(rows.size() * size_t(k));
+    HIPCHK(hipMemcpyAsync(h.data(), gout_.p, h.size() * sizeof(double2), hipMemcpyDeviceToHost, st_));
     HIPCHK(hipStreamSynchronize(st_));
     for (size_t i = 0; i < h.size(); ++i) out[i] = cd(h[i].x, h[i].y);
   }
@@ -106,17 +115,32 @@ class DevEngine final : public Engine {
   OpP dense_diag(std::vector<DenseDiag> blocks) override;
 
   // program workspace, grown on demand (programs run one at a time on the stream)
-  float2 *work(int64_t rows, int R) {
-    const size_t bytes = size_t(std::max<int64_t>(rows, 1)) * size_t(R) * sizeof(float2);
-    if (work_.bytes < bytes) work_.alloc(bytes);
-    return work_.as<float2>();
+  double2 *work(int64_t rows, int R) {
+    grow(work_, size_t(std::max<int64_t>(rows, 1)) * size_t(R) * sizeof(double2));
+    return work_.as<double2>();
   }
 
  private:
+  // grow-only device buffers: an allocation (and the free before it) synchronizes the
+  // device, so staging buffers are only ever enlarged
+  static void grow(DevBuf &b, size_t bytes) {
+    if (b.bytes < bytes) b.alloc(std::max(bytes, b.bytes + b.bytes / 4));
+  }
+  // copy host data into a staging buffer; the stream is synchronized so the caller's
+  // host vector may go away
+  void stage(DevBuf &b, const void *src, size_t bytes) {
+    grow(b, bytes);
+    if (bytes) {
+      HIPCHK(hipMemcpyAsync(b.p, src, bytes, hipMemcpyHostToDevice, st_));
+      HIPCHK(hipStreamSynchronize(st_));
+    }
+  }
+
   hipStream_t st_;
   int mc_;
   std::multimap<size_t, DevBuf> pool_;
-  DevBuf work_, flags_, slots_;
+  std::map<RowSet, DevBuf> masks_;
+  DevBuf work_, slots_, grows_, gq0_, gout_;
 };
 
 DevMv::~DevMv() {
@@ -135,7 +159,11 @@ class DevProgOp final : public LinOp {
     D.zero(y);
     const Program &p = tr ? trans : fwd;
     if (p.launches.empty()) return;
-    run_program(p, arena.p, FT_C64, dv(x).p(), D.work(p.t_rows, x.R), dv(y).p(), x.R, D.stream());
+    double2 *T = D.work(p.t_rows, x.R);
+    for (const Launch &ln : p.launches)
+      launch_grouped_f64(p.segs.as<Seg>(), p.pairs.as<Pair>(), p.rowmap.as<RowMap>(), ln.s0, ln.ns,
+                         arena.as<float2>(), dv(x).p(), T, ln.out ? dv(y).p() : T, x.R, ln.beta,
+                         D.stream());
     HIPCHK(hipGetLastError());
   }
 };

@@ -6,12 +6,15 @@
 // then per level D^{-1} B reconstructed from products with random vectors (line 7) and
 // X_tau by the butterfly Sherman-Morrison-Woodbury recursion of Algorithm 2 (line 8).
 // The X_tau butterflies (four per node, on the children pairs, L_H - l - 1 levels) are
-// packed into one grouped-GEMM program per level; with precond_dense_levels = d the
-// leaf inverses and the d lowest levels are multiplied out into the dense inverses of
-// the level L_H - d nodes (one launch instead of many short ones).
+// packed into one grouped-GEMM program per level.  With precond_dense_levels = d the
+// recursion starts from the dense inverses of the level L_H - d nodes' diagonal blocks
+// (computed directly, host FP64) instead of the 64-point leaves: the d lowest levels are
+// exact, which removes them from the chain of approximate inverses each level's
+// reconstruction multiplies through, and their apply is one launch.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 #include "construct_dev.h"
@@ -59,38 +62,6 @@ uint32_t to_bf16_pair(cd v) {
   return cv(float(v.real())) | (cv(float(v.imag())) << 16);
 }
 
-// The dense inverses of the level-lb nodes as the multiplicative form of the levels
-// built so far maps unit probes: column j of every node at once (the operator is
-// block diagonal over those nodes).
-std::vector<DenseDiag> materialize(Engine &E, const LinOp &Dinv, const Tree &t, int lb) {
-  const int64_t nn = int64_t(1) << lb;
-  int R = 0;
-  for (int64_t g = 0; g < nn; ++g) R = std::max(R, t.node_hi(lb, g) - t.node_lo(lb, g));
-  std::vector<int32_t> col(size_t(t.n), -1);
-  for (int64_t g = 0; g < nn; ++g)
-    for (int32_t r = t.node_lo(lb, g); r < t.node_hi(lb, g); ++r) col[size_t(r)] = r - t.node_lo(lb, g);
-  MvP X = E.make(R), Y = E.make(R);
-  E.fill_unit(*X, col);
-  Dinv.apply(E, false, *X, *Y);
-  std::vector<DenseDiag> out(static_cast<size_t>(nn));
-  std::vector<cd> buf;
-  for (int64_t g = 0; g < nn; ++g) {
-    const int32_t lo = t.node_lo(lb, g), hi = t.node_hi(lb, g);
-    const int m = hi - lo;
-    Gather gq;
-    gq.q0 = 0;
-    for (int32_t r = lo; r < hi; ++r) gq.rows.push_back(r);
-    E.gather(*Y, {gq}, R, buf);  // row i of the node: R values
-    DenseDiag &d = out[size_t(g)];
-    d.lo = lo;
-    d.D.m = d.D.n = m;
-    d.D.v.resize(size_t(m) * m);
-    for (int j = 0; j < m; ++j)
-      for (int i = 0; i < m; ++i) d.D.v[size_t(j) * m + i] = cf(buf[size_t(i) * R + j]);
-  }
-  return out;
-}
-
 }  // namespace
 
 void build_precond(hodbf_op &op, const std::vector<Butterfly> &plan, hipStream_t st) {
@@ -108,20 +79,23 @@ void build_precond(hodbf_op &op, const std::vector<Butterfly> &plan, hipStream_t
   const bool wantb16 = (p.precond_prec & HODBF_P_BF16) != 0;
   const bool wanth16 = (p.precond_prec & HODBF_P_FP16) != 0;
 
-  // Algorithm 1 on the device; sketch chunks of at most ~2 GiB per multi-vector
-  const int mc = int(std::clamp<int64_t>((int64_t(1) << 31) / (8 * std::max<int64_t>(t.n, 1)), 32, 2048)) & ~31;
+  // Algorithm 1 on the device; sketch chunks of at most ~2 GiB per multi-vector (complex
+  // FP64)
+  const int mc = int(std::clamp<int64_t>((int64_t(1) << 31) / (16 * std::max<int64_t>(t.n, 1)), 32, 2048)) & ~31;
   auto E = make_device_engine(&t, st, mc);
   RbfOpts o;
   o.chi = p.tol_fact;
   o.seed = p.seed ^ 0xA5A5A5A5ull;
+  // intermediate reconstructions (A22^{-1}, the Schur update, the inner products of
+  // the recursion) at 1e-2 chi_fact: their errors are amplified by the inverses
+  // the later steps multiply through; HODBF_CHI_INNER overrides
+  o.chi_inner = 1e-2 * o.chi;
+  if (const char *e = std::getenv("HODBF_CHI_INNER")) o.chi_inner = std::atof(e);
+  if (const char *e = std::getenv("HODBF_CHI_DECAY")) o.chi_decay = std::atof(e);
   PrecondBuild pb = invert_hodbf(
-      *E, op.ker, pd.min_level, [&](int l) { return forward_offdiag_explicit(t, plan, op.ker, l); }, o);
+      *E, op.ker, pd.min_level, lb,
+      [&](int l) { return forward_offdiag_explicit(t, plan, op.ker, l); }, o);
   std::vector<DenseDiag> first = std::move(pb.leaf_inv);
-  if (dl > 0) {
-    std::vector<OpP> lower(pb.ops.begin(), pb.ops.begin() + dl);
-    OpP Dinv = mult_inverse(*E, pb.leaf_op, lower);
-    first = materialize(*E, *Dinv, t, lb);
-  }
   pb.ops.clear();
   pb.leaf_op.reset();
   E.reset();
@@ -182,8 +156,8 @@ void build_precond(hodbf_op &op, const std::vector<Butterfly> &plan, hipStream_t
   }
   int maxr = 0;
   pd.levels.clear();
-  for (size_t i = size_t(dl); i < pb.levels.size(); ++i) {
-    const int l = LH - 1 - int(i);
+  for (size_t i = 0; i < pb.levels.size(); ++i) {
+    const int l = lb - 1 - int(i);
     std::vector<const Butterfly *> ptrs;
     for (const Butterfly &bf : pb.levels[i]) {
       ptrs.push_back(&bf);

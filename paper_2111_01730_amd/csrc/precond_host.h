@@ -18,9 +18,9 @@ std::vector<Butterfly> forward_offdiag_explicit(const Tree &t, const std::vector
                                                const Kernel &ker, int l);
 
 // Block table (rows of BlockRec) and values of a host-built preconditioner: leaf
-// inverses as kind 0 at level L_H, every X_tau butterfly's V^0 / W / B blocks with
+// inverses as kind 0 at the recursion's leaf level, every X_tau butterfly's V^0 / W / B blocks with
 // (l, i, ca, cb) = (tree level of tau, tau, child row, child column).
-void export_precond_build(const PrecondBuild &pb, int LH, std::vector<BlockRec> &table,
+void export_precond_build(const PrecondBuild &pb, std::vector<BlockRec> &table,
                           std::vector<cd> &vals);
 
 }  // namespace hodbf

@@ -2,6 +2,7 @@
 // randomized reconstruction, complex FP64 on the CPU) for verification without a GPU,
 // and helpers shared with the device construction: the forward operator's off-diagonal
 // butterflies with explicit outer factors, and the block-table export.
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 
@@ -57,7 +58,7 @@ std::vector<Butterfly> forward_offdiag_explicit(const Tree &t, const std::vector
   return out;
 }
 
-void export_precond_build(const PrecondBuild &pb, int LH, std::vector<BlockRec> &table,
+void export_precond_build(const PrecondBuild &pb, std::vector<BlockRec> &table,
                           std::vector<cd> &vals) {
   table.clear();
   vals.clear();
@@ -68,7 +69,7 @@ void export_precond_build(const PrecondBuild &pb, int LH, std::vector<BlockRec> 
   };
   for (size_t g = 0; g < pb.leaf_inv.size(); ++g) {
     const Mat &D = pb.leaf_inv[g].D;
-    table.push_back({0, LH, int64_t(g), 0, 0, 0, 0, 0, D.m, D.n, put(D), D.m});
+    table.push_back({0, pb.leaf_level, int64_t(g), 0, 0, 0, 0, 0, D.m, D.n, put(D), D.m});
   }
   for (const auto &lvl : pb.levels)
     for (const Butterfly &bf : lvl) {
@@ -127,7 +128,8 @@ extern "C" hodbf_status hodbf_precond_probe(const hodbf_build_params *params, in
     std::vector<double> key = {double(programs), double(params->nx), double(params->ny), double(params->nz),
                                params->h, params->k0, params->tol_con, params->tol_fact,
                                double(params->leaf_size), double(params->seed),
-                               double(params->precond_min_level)};
+                               double(params->precond_min_level),
+                               double(params->precond_dense_levels)};
     if (params->eps_r && n > 0) key.insert(key.end(), params->eps_r, params->eps_r + 2 * n);
     if (key != g_pp_key) {
       if (!(params->tol_fact > 0 && params->tol_fact < 1)) fail(HODBF_E_ARG, "tol_fact must lie in (0, 1)");
@@ -136,12 +138,20 @@ extern "C" hodbf_status hodbf_precond_probe(const hodbf_build_params *params, in
       auto E = make_host_engine(&fp.tree, 256, programs);
       RbfOpts o;
       o.chi = params->tol_fact;
+      // intermediate reconstructions (A22^{-1}, the Schur update, the inner products of
+      // the recursion) at 1e-2 chi_fact: their errors are amplified by the inverses
+      // the later steps multiply through; HODBF_CHI_INNER overrides
+      o.chi_inner = 1e-2 * o.chi;
+      if (const char *e = std::getenv("HODBF_CHI_INNER")) o.chi_inner = std::atof(e);
+      if (const char *e = std::getenv("HODBF_CHI_DECAY")) o.chi_decay = std::atof(e);
       o.seed = params->seed ^ 0xA5A5A5A5ull;
       const int minl = std::min(params->precond_min_level, fp.tree.depth);
+      const int lb = fp.tree.depth - std::min(params->precond_dense_levels, fp.tree.depth);
+      if (lb < minl) fail(HODBF_E_ARG, "precond_dense_levels reaches above precond_min_level");
       PrecondBuild pb = invert_hodbf(
-          *E, fp.ker, minl, [&](int l) { return forward_offdiag_explicit(fp.tree, fp.bfs, fp.ker, l); }, o);
+          *E, fp.ker, minl, lb, [&](int l) { return forward_offdiag_explicit(fp.tree, fp.bfs, fp.ker, l); }, o);
       g_pp_perm = fp.tree.perm;
-      export_precond_build(pb, fp.tree.depth, g_pp_table, g_pp_vals);
+      export_precond_build(pb, g_pp_table, g_pp_vals);
       g_pp_stats = {pb.reconstructions, pb.woodbury, pb.stats.sketch_cols, pb.stats.ids,
                     pb.stats.max_rank, pb.stats.applies};
       g_pp_key = key;

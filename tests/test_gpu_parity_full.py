@@ -63,7 +63,7 @@ def test_c2_forward_full_size_matches_exported_factors(c2, which, split, kind):
     ratio, col_ref, col_abs = bounds.check(y, ref, absref, dims, split)
     tol = bounds.normwise_tolerance(dims, split)
     print(f"[c2 forward which {which}, {kind}: {len(dims)} stages, element-wise error / "
-          f"bound {ratio:.3f}, column error {col_ref:.2e} (tolerance {tol:.2e})]", flush=True)
+          f"bound {ratio:.2e}, column error {col_ref:.2e} (tolerance {tol:.2e})]", flush=True)
     assert ratio <= 1.0
     assert col_ref <= tol
 
@@ -79,12 +79,13 @@ def test_c2_precond_dense_bottom_full_size_matches_exported_factors(c2, which, s
     ref = c2["pre"].apply_tree(xt)
     absref = bounds.absolute_precond(c2["pre"]).apply_tree(np.abs(xt))
     dims = bounds.precond_stage_dims(c2["ptab"], c2["st"]["levels"])
+    assert np.isfinite(z).all(), "non-finite preconditioner output"
     ratio, col_ref, col_abs = bounds.check(z, ref, absref, dims, split)
     tol = bounds.normwise_tolerance(dims, split)
     # the multiplicative form cancels (its output is much smaller than its abs chain), so
     # the norm-wise bound is taken against the abs chain
     print(f"[c2 preconditioner which {which}, {kind}: {len(dims)} dependent stages, "
-          f"element-wise error / bound {ratio:.3f}, column error vs abs chain {col_abs:.2e} "
+          f"element-wise error / bound {ratio:.2e}, column error vs abs chain {col_abs:.2e} "
           f"(tolerance {tol:.2e}), vs exact {col_ref:.2e}]", flush=True)
     assert ratio <= 1.0
     assert col_abs <= tol

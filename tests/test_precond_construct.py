@@ -14,7 +14,10 @@ hodbf_precond_probe (complex FP64, no GPU) and checked against the oracle:
   descriptors, the same results;
 * the number of reconstructions is what the recursion of Algorithm 2 predicts (one for
   line 7 of Algorithm 1 per level, then per BF_SMW call: A22^{-1}, the Schur update
-  and A11^{-1} recursively, and the final product)."""
+  and A11^{-1} recursively, and the final product);
+* started from the dense inverses of larger nodes (precond_dense_levels), those blocks
+  are the inverses of the diagonal blocks of the dense operator, only the levels above
+  them are reconstructed, and the preconditioner is no worse."""
 import numpy as np
 import pytest
 
@@ -25,18 +28,21 @@ from synth.workloads import small_case
 _lib = pytest.importorskip("paper_2111_01730_amd._lib")
 
 
-def _probe(g, chi_con, chi_fact, seed=1, programs=False):
+def _probe(g, chi_con, chi_fact, seed=1, programs=False, dense=0):
     """programs: run every product through the device path's packed grouped-GEMM
-    programs (forward and transposed), interpreted on the host."""
+    programs (forward and transposed), interpreted on the host.  dense: the recursion
+    starts from the dense inverses of the nodes that many levels above the leaves."""
     from tests.plan_tools import precond_from_export
-    p = _lib.make_params(g, chi_con, chi_fact, precond_prec=1, seed=seed)
+    p = _lib.make_params(g, chi_con, chi_fact, precond_prec=1, seed=seed,
+                         precond_dense_levels=dense)
     o = 16 if programs else 0
     perm = _lib.probe(p, 0 + o, np.int32, "hodbf_precond_probe")
     tab = _lib.probe(p, 3 + o, np.int64, "hodbf_precond_probe").reshape(-1, 12)
     vals = _lib.probe(p, 4 + o, np.complex128, "hodbf_precond_probe")
     stats = _lib.probe(p, 7 + o, np.int64, "hodbf_precond_probe")
-    depth = int(tab[tab[:, 0] == 0][0, 1])
-    return precond_from_export(g, perm, tab, vals, depth), stats, depth
+    from oracle.tree import depth_for
+    lb = int(tab[tab[:, 0] == 0][0, 1])  # level of the dense inverses
+    return precond_from_export(g, perm, tab, vals, depth_for(g.n, 64)), stats, lb
 
 
 def _rel(a, b):
@@ -75,7 +81,7 @@ def test_quality_matches_the_oracle(ragged, chi_fact, programs):
     assert np.all(_rel(P.apply(x), po.apply(x)) <= 30 * chi_fact)
 
 
-def _predicted_reconstructions(depth):
+def _predicted_reconstructions(depth, top=None):
     def smw(lc, has22):
         return inv(lc, has22) + inv(lc, True) + 1
 
@@ -86,7 +92,7 @@ def _predicted_reconstructions(depth):
             return 1
         return 1 + smw(lc - 2, True)
 
-    return sum(1 + smw(depth - l - 1, False) for l in range(depth))
+    return sum(1 + smw(depth - l - 1, False) for l in range(depth if top is None else top))
 
 
 @pytest.mark.parametrize("sides", [(8, 8, 8), (10, 9, 8), (16, 16, 8)])
@@ -95,3 +101,24 @@ def test_reconstruction_count_follows_algorithm_2(sides):
     _, stats, depth = _probe(c["grid"], 1e-4, 1e-2)
     assert int(stats[0]) == _predicted_reconstructions(depth)
     assert _predicted_reconstructions(3) == 12 and _predicted_reconstructions(4) == 18
+
+
+def test_dense_bottom_levels(ragged):
+    c, Z = ragged
+    g = c["grid"]
+    P0, _, depth = _probe(g, 1e-6, 1e-2)
+    P, stats, lb = _probe(g, 1e-6, 1e-2, dense=2)
+    assert lb == depth - 2
+    # the recursion's leaves: inverses of Z(tau, tau) in tree order (FP32 storage)
+    Zt = Z[np.ix_(P.tree.perm, P.tree.perm)]
+    for i, (lo, hi) in enumerate(P.tree.ranges[lb]):
+        inv = np.linalg.inv(Zt[lo:hi, lo:hi])
+        assert np.linalg.norm(P.Dinv[i] - inv) <= 1e-6 * np.linalg.norm(inv)
+    # only the levels above them are built by Algorithm 1
+    assert int(stats[0]) == _predicted_reconstructions(depth, top=lb)
+    x = c["x"]
+    assert _rel(P.apply(Z @ x), x).max() <= _rel(P0.apply(Z @ x), x).max()
+    # d = L_H: the root's dense inverse, Z^{-1} to FP32 storage
+    Pr, stats_r, lr = _probe(g, 1e-6, 1e-2, dense=depth)
+    assert lr == 0 and int(stats_r[0]) == 0
+    assert np.all(_rel(Pr.apply(Z @ x), x) <= 1e-5)
