@@ -809,7 +809,7 @@ namespace {
 
 struct Ctx {
   Engine &E;
-  RbfOpts o;  // tolerances of the level being built
+  const RbfOpts &o;
   PrecondBuild &pb;
   // final sketch widths of earlier reconstructions of the same shape and role: the next
   // one starts there instead of doubling up from k0 again
@@ -976,11 +976,6 @@ PrecondBuild invert_hodbf(Engine &E, const Kernel &ker, int min_level, int leaf_
        seconds_since(t0));
   for (int l = leaf_level - 1; l >= min_level; --l) {
     auto tl = std::chrono::steady_clock::now();
-    // tolerances of this level: chi_fact / decay^l (an error made at level l reaches the
-    // root through the l levels above it, each multiplying it by about ||A_tau^{-1}||)
-    const double lf = std::pow(o.chi_decay, -double(l));
-    c.o.chi = o.chi * lf;
-    c.o.chi_inner = o.chi_inner * lf;
     const int Lb = LH - l - 1;
     std::vector<int64_t> nodes(static_cast<size_t>(int64_t(1) << l));
     for (size_t i = 0; i < nodes.size(); ++i) nodes[i] = int64_t(i);

@@ -109,7 +109,6 @@ struct Target {
 struct RbfOpts {
   double chi = 1e-4;
   double chi_inner = 0;  // tolerance of intermediate reconstructions (0: chi)
-  double chi_decay = 1;  // level l of Algorithm 1 runs at chi / chi_decay^l (and chi_inner)
   uint64_t seed = 1;
   int k0 = 32;        // first sketch width per slot
   int k0_side[2] = {0, 0};  // first widths of the column and row sides (0: k0)

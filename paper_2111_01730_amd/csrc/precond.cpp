@@ -91,7 +91,6 @@ void build_precond(hodbf_op &op, const std::vector<Butterfly> &plan, hipStream_t
   // the later steps multiply through; HODBF_CHI_INNER overrides
   o.chi_inner = 1e-2 * o.chi;
   if (const char *e = std::getenv("HODBF_CHI_INNER")) o.chi_inner = std::atof(e);
-  if (const char *e = std::getenv("HODBF_CHI_DECAY")) o.chi_decay = std::atof(e);
   PrecondBuild pb = invert_hodbf(
       *E, op.ker, pd.min_level, lb,
       [&](int l) { return forward_offdiag_explicit(t, plan, op.ker, l); }, o);

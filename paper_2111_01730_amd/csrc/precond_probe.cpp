@@ -143,7 +143,6 @@ extern "C" hodbf_status hodbf_precond_probe(const hodbf_build_params *params, in
       // the later steps multiply through; HODBF_CHI_INNER overrides
       o.chi_inner = 1e-2 * o.chi;
       if (const char *e = std::getenv("HODBF_CHI_INNER")) o.chi_inner = std::atof(e);
-      if (const char *e = std::getenv("HODBF_CHI_DECAY")) o.chi_decay = std::atof(e);
       o.seed = params->seed ^ 0xA5A5A5A5ull;
       const int minl = std::min(params->precond_min_level, fp.tree.depth);
       const int lb = fp.tree.depth - std::min(params->precond_dense_levels, fp.tree.depth);
