@@ -122,6 +122,20 @@ hodbf_status hodbf_apply(const hodbf_op *op, int32_t nrhs, hodbf_dtype dtype,
                          const void *x, int64_t ldx, void *y, int64_t ldy, void *stream);
 
 /*
+ * hodbf_apply_noalloc -- the product of hodbf_apply (same arguments, same result bit for
+ * bit) for callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation.  It allocates nothing; its
+ * temporaries (tree-order copies of x and y and the stage workspace, 2 * 8 N nrhs +
+ * 8 nrhs * (stage rows) bytes, each part rounded up to 256) live in a static scratch
+ * array of 64 MiB that every GPU the library runs on holds until the process ends.
+ * E_ARG if these sizes need more than that (use fewer right-hand sides per call).
+ * Every call on one GPU shares that GPU's array: calls that overlap on one GPU (other
+ * streams, other threads) race and must be ordered by the caller.
+ */
+hodbf_status hodbf_apply_noalloc(const hodbf_op *op, int32_t nrhs, hodbf_dtype dtype,
+                                 const void *x, int64_t ldx, void *y, int64_t ldy, void *stream);
+
+/*
  * hodbf_precond_apply -- y = P x with P ~ Z^{-1}: the leaf inverses D_tau^{-1}
  * followed, level by level towards the root, by z(tau) <- (I + X_tau) z(tau)
  * (Algorithm 1 unrolled).  Uses the default arithmetic: the FP32 copy with split-BF16

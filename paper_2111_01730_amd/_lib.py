@@ -78,6 +78,7 @@ def lib():
     L.hodbf_build.argtypes = [C.POINTER(BuildParams), C.POINTER(vp)]
     L.hodbf_apply.argtypes = [vp, i32, i32, vp, i64, vp, i64, vp]
     L.hodbf_precond_apply.argtypes = [vp, i32, i32, vp, i64, vp, i64, vp]
+    L.hodbf_apply_noalloc.argtypes = [vp, i32, i32, vp, i64, vp, i64, vp]
     L.vie_solve.argtypes = [vp, i32, vp, i64, vp, i64, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
     L.hodbf_plane_wave.argtypes = [vp, i32, C.POINTER(C.c_double), vp, i64, vp]
     L.hodbf_solve_workspace.argtypes = [vp, i32, C.POINTER(SolveOpts), C.POINTER(C.c_size_t)]
@@ -90,7 +91,7 @@ def lib():
     L.hodbf_free.argtypes = [vp]
     L.hodbf_free.restype = None
     L.hodbf_last_error.restype = C.c_char_p
-    for name in ["hodbf_build", "hodbf_apply", "hodbf_precond_apply", "vie_solve", "hodbf_apply_tree",
+    for name in ["hodbf_build", "hodbf_apply", "hodbf_apply_noalloc", "hodbf_precond_apply", "vie_solve", "hodbf_apply_tree",
                  "hodbf_plane_wave", "hodbf_solve_workspace", "hodbf_stats", "hodbf_export", "hodbf_plan_probe",
                  "hodbf_precond_probe", "hodbf_set_allocator"]:
         getattr(L, name).restype = C.c_int
