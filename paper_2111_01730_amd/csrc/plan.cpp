@@ -30,15 +30,19 @@ struct ZSource final : EntrySource {
 // Rows of [r0, r1) used for one ID of M = A(rows, cols) and their weights.
 // Few rows: all of them (the ID is then exact in the sense of eq. (ID)).
 // Otherwise: every row inside the columns' bounding box grown by two voxels (the
-// near field that dominates weakly admissible blocks), plus 2*nc+16 uniform random
-// rows from the rest, weighted by sqrt(remaining / drawn) so that Frobenius norms of
-// the sample estimate those of the full block and the chi test keeps its meaning.
+// near field that dominates weakly admissible blocks), plus mult * (2*nc+16) uniform
+// random rows from the rest, weighted by sqrt(remaining / drawn) so that Frobenius
+// norms of the sample estimate those of the full block and the chi test keeps its
+// meaning.  rest receives the far rows that were not drawn (empty when every row is
+// used), from which the ID is then checked.
 void pick_rows(const Tree &t, int32_t r0, int32_t r1, const std::vector<int32_t> &cols,
-               uint64_t seed, std::vector<int32_t> &rows, std::vector<double> &wt) {
+               uint64_t seed, int mult, std::vector<int32_t> &rows, std::vector<double> &wt,
+               std::vector<int32_t> &rest) {
   const int32_t m = r1 - r0;
   const int nc = int(cols.size());
   rows.clear();
   wt.clear();
+  rest.clear();
   if (m <= 2 * nc + 48) {
     rows.resize(m);
     std::iota(rows.begin(), rows.end(), r0);
@@ -66,7 +70,7 @@ void pick_rows(const Tree &t, int32_t r0, int32_t r1, const std::vector<int32_t>
       far.push_back(r);
     }
   }
-  const int64_t want = std::min<int64_t>(far.size(), 2 * int64_t(nc) + 16);
+  const int64_t want = std::min<int64_t>(far.size(), int64_t(mult) * (2 * int64_t(nc) + 16));
   if (want == int64_t(far.size())) {
     for (int32_t r : far) {
       rows.push_back(r);
@@ -85,6 +89,32 @@ void pick_rows(const Tree &t, int32_t r0, int32_t r1, const std::vector<int32_t>
     rows.push_back(far[i]);
     wt.push_back(w);
   }
+  rest.assign(far.begin() + want, far.end());
+}
+
+// Squared Frobenius norm of A(rows, cols) - A(rows, cols(J)) V over up to 32 rows drawn
+// from `rest`, scaled to all of `rest` (V: r x nc column-major, V(:, J) = I).
+double check_rows_residual2(const EntrySource &src, const std::vector<int32_t> &rest,
+                            const std::vector<int32_t> &cols, const std::vector<int> &J,
+                            const std::vector<cd> &V, int rk, uint64_t seed) {
+  const int nc = int(cols.size());
+  std::vector<int32_t> pool(rest);
+  const int nv = int(std::min<size_t>(pool.size(), 32));
+  uint64_t s = seed;
+  for (int i = 0; i < nv; ++i) {
+    const size_t j = size_t(i) + size_t(splitmix(s) % uint64_t(pool.size() - size_t(i)));
+    std::swap(pool[size_t(i)], pool[j]);
+  }
+  std::vector<cd> Mv(size_t(nv) * nc);
+  src.fill(pool.data(), nv, cols.data(), nc, Mv.data());
+  double r2 = 0;
+  for (int i = 0; i < nv; ++i)
+    for (int c = 0; c < nc; ++c) {
+      cd e = Mv[size_t(c) * nv + i];
+      for (int k = 0; k < rk; ++k) e -= Mv[size_t(J[k]) * nv + i] * V[size_t(c) * rk + k];
+      r2 += std::norm(e);
+    }
+  return r2 * double(rest.size()) / double(std::max(nv, 1));
 }
 
 uint64_t job_seed(uint64_t seed, int64_t bf, int l, int64_t a, int64_t b) {
@@ -109,7 +139,7 @@ void build_butterflies(const EntrySource &src, const Tree &t, std::vector<Butter
     int64_t bf, a, b;
     double cost;
   };
-  int64_t ids = 0;
+  int64_t ids = 0, redo = 0;
   for (int l = 0; l <= Lmax; ++l) {
     std::vector<Job> jobs;
     for (size_t k = 0; k < bfs.size(); ++k) {
@@ -141,7 +171,7 @@ void build_butterflies(const EntrySource &src, const Tree &t, std::vector<Butter
     ids += int64_t(jobs.size());
 #pragma omp parallel
     {
-      std::vector<int32_t> cols, rows;
+      std::vector<int32_t> cols, rows, rest;
       std::vector<double> wt;
       std::vector<cd> M, V;
       std::vector<int> J;
@@ -169,13 +199,30 @@ void build_butterflies(const EntrySource &src, const Tree &t, std::vector<Butter
         out.n = nc;
         std::vector<int32_t> sk;
         if (nc > 0) {
-          pick_rows(*src.tree, r0, r1, cols, job_seed(seed, jb.bf, l, jb.a, jb.b), rows, wt);
-          const int nr = int(rows.size());
-          M.resize(size_t(nr) * nc);
-          src.fill(rows.data(), nr, cols.data(), nc, M.data());
-          for (int c = 0; c < nc; ++c)
-            for (int r = 0; r < nr; ++r) M[size_t(c) * nr + r] *= wt[r];
-          const int rk = id_cpqr(M.data(), nr, nc, chi, J, V);
+          // the ID of the sampled rows is checked on rows it did not see: if the residual
+          // estimated from them exceeds 2 chi ||M||_F (the sampled rows' own residual is
+          // just under chi ||M||_F, and 32 rows estimate the rest only roughly), the random
+          // sample doubles and the ID is redone (at most three times)
+          const uint64_t js = job_seed(seed, jb.bf, l, jb.a, jb.b);
+          int rk = 0;
+          for (int mult = 1;; mult *= 2) {
+            pick_rows(*src.tree, r0, r1, cols, js, mult, rows, wt, rest);
+            const int nr = int(rows.size());
+            M.resize(size_t(nr) * nc);
+            src.fill(rows.data(), nr, cols.data(), nc, M.data());
+            double norm2 = 0;
+            for (int c = 0; c < nc; ++c)
+              for (int r = 0; r < nr; ++r) {
+                M[size_t(c) * nr + r] *= wt[r];
+                norm2 += std::norm(M[size_t(c) * nr + r]);
+              }
+            rk = id_cpqr(M.data(), nr, nc, chi, J, V);
+            if (rest.empty() || mult >= 8) break;
+            const double res2 = check_rows_residual2(src, rest, cols, J, V, rk, js ^ 0xC0FFEEull);
+            if (res2 <= 4 * chi * chi * norm2) break;
+#pragma omp atomic
+            ++redo;
+          }
           out.m = rk;
           out.v.assign(V.begin(), V.end());
           sk.resize(rk);
@@ -197,6 +244,7 @@ void build_butterflies(const EntrySource &src, const Tree &t, std::vector<Butter
     for (int64_t a = 0; a < na; ++a) bf.bskel[size_t(a)] = skel[k][size_t(a)];
   }
   if (id_count) *id_count += ids;
+  if (redo) logf("  row sampling: %lld IDs redone with a doubled sample", (long long)redo);
 }
 
 void validate_params(const hodbf_build_params &p) {

@@ -66,6 +66,19 @@ def test_sampled_construction_accuracy_c1_cube():
     assert np.all(err <= 10 * cfg["tol"]), err
 
 
+def test_sampled_construction_accuracy_high_contrast():
+    # 32x16x16 voxels at h = lambda/8 with i.i.d. eps_r U[2, 10] (the benchmark's regime):
+    # most blocks are sampled, and each sampled ID is checked on rows it did not see
+    from synth.workloads import make_grid as mg
+    rng = np.random.default_rng(12)
+    g = mg(32, 16, 16, 1.0 / 8, rng.uniform(2.0, 10.0, 32 * 16 * 16))
+    op = hodbf_from_export(g, *_probe_all(g, 1e-4))
+    x = rng.standard_normal((g.n, 2)) + 1j * rng.standard_normal((g.n, 2))
+    y = vie.fft_matvec(g, x)
+    err = np.linalg.norm(op.apply(x) - y, axis=0) / np.linalg.norm(y, axis=0)
+    assert np.all(err <= 10 * 1e-4), err
+
+
 def test_free_space_plan_has_zero_ranks():
     g = make_grid(8, 8, 8, 0.125, 1.0)
     perm, table, vals, skel = _probe_all(g, 1e-4)
