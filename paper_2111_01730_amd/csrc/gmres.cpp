@@ -8,6 +8,7 @@
 #include <type_traits>
 #include <vector>
 
+#include "construct_dev.h"
 #include "op.h"
 
 namespace hodbf {
@@ -55,6 +56,22 @@ static int precond_ftype(const hodbf_op &op, int use_precond) {
   fail(HODBF_E_ARG, "unknown use_precond");
 }
 
+// The last few columns of a solve (at most kF64Cols still iterating) run their products
+// with Z in FP64 arithmetic over the FP32-stored factors, inside the Arnoldi process and
+// for the true residual.  Products that round their input and accumulate in FP32 err by
+// about u32 ||Z|| ||z||; for a column whose Krylov vectors reach the ill-conditioned
+// directions that P amplifies, that error approaches the residual still to be removed,
+// and the column stalls just above tol, each restart undoing what the last one gained.
+constexpr int kF64Cols = 4;
+
+// y = Z_con x in FP64 (x, y tree order, R columns interleaved; T: stage workspace)
+static void forward_f64(const hodbf_op &op, const double2 *x, double2 *T, double2 *y, int R,
+                        hipStream_t st) {
+  for (const Launch &ln : op.fwd.launches)
+    launch_grouped_f64(op.fwd.segs.as<Seg>(), op.fwd.pairs.as<Pair>(), op.fwd.rowmap.as<RowMap>(),
+                       ln.s0, ln.ns, op.fwdF.as<float2>(), x, T, ln.out ? y : T, R, ln.beta, st);
+}
+
 // Device workspace of one solve: every buffer solve_impl carves, each rounded up to 256
 // bytes plus 256 of alignment slack.
 static size_t solve_workspace(const hodbf_op &op, int R, int m, bool pre) {
@@ -76,6 +93,7 @@ static size_t solve_workspace(const hodbf_op &op, int R, int m, bool pre) {
   add(NR * 8);                  // wf
   add(NR * 8);                  // vf
   add(size_t(std::max<int64_t>(wrows, 1)) * R * 8);  // apply workspace
+  add(size_t(std::max<int64_t>(forward_work_rows(op), 1)) * std::min(R, kF64Cols) * 16);  // FP64 apply workspace
   add(size_t(nblk) * (m + 1) * R * 16);             // partials
   add(size_t(m + 1) * m * R * 16);                  // H
   add(size_t(m) * R * 16 * 2);                      // cs, sn
@@ -109,6 +127,8 @@ static void solve_impl(const hodbf_op &op, int R, const void *b, int64_t ldb, vo
   double2 *w = cv.take<double2>(NR);
   float2 *wf = cv.take<float2>(NR), *vf = cv.take<float2>(NR);
   float2 *work = cv.take<float2>(size_t(std::max<int64_t>(wrows, 1)) * R);
+  double2 *work64 = cv.take<double2>(size_t(std::max<int64_t>(forward_work_rows(op), 1)) *
+                                     std::min(R, kF64Cols));
   double2 *partial = cv.take<double2>(size_t(nblk) * (m + 1) * R);
   GmresState gs;
   gs.m = m;
@@ -165,6 +185,7 @@ static void solve_impl(const hodbf_op &op, int R, const void *b, int64_t ldb, vo
   std::vector<double> bn2, rn2;
   norms2(bt, bn2);
   std::vector<double> bnorm(static_cast<size_t>(R)), relres(static_cast<size_t>(R), 0.0);
+  std::vector<double> target(static_cast<size_t>(R), 1.0);
   std::vector<int32_t> active(static_cast<size_t>(R)), iters(static_cast<size_t>(R), 0);
   for (int q = 0; q < R; ++q) {
     bnorm[size_t(q)] = std::sqrt(bn2[size_t(q)]);
@@ -191,7 +212,10 @@ static void solve_impl(const hodbf_op &op, int R, const void *b, int64_t ldb, vo
     launch_gather_cols<double2>(rt, n, R, colidx, Ra, w, st);
     launch_gather_cols<double2>(xt, n, R, colidx, Ra, xc, st);
     std::vector<double> bsub(static_cast<size_t>(Ra));
-    for (int k = 0; k < Ra; ++k) bsub[size_t(k)] = bnorm[size_t(act[size_t(k)])];
+    // the Arnoldi estimate compares against tol times this norm: halved for a column
+    // whose last cycle ended just above tol (see below)
+    for (int k = 0; k < Ra; ++k)
+      bsub[size_t(k)] = bnorm[size_t(act[size_t(k)])] * target[size_t(act[size_t(k)])];
     std::vector<int32_t> ones(static_cast<size_t>(Ra), 1);
     upload(gs.bnorm, bsub.data(), size_t(Ra) * 8);
     upload(gs.active, ones.data(), size_t(Ra) * 4);
@@ -221,8 +245,13 @@ static void solve_impl(const hodbf_op &op, int R, const void *b, int64_t ldb, vo
       launch_c128_to_c64(vj, vf, NRc, st);
       if (pre_ft >= 0) apply_precond_tree(op, pre_ft, vf, zj, work, Rc, st);
       else HIPCHK(hipMemcpyAsync(zj, vf, NRc * 8, hipMemcpyDeviceToDevice, st));
-      apply_forward_tree(op, zj, wf, work, Rc, st);
-      launch_c64_to_c128(wf, w, NRc, st);
+      if (Rc <= kF64Cols) {
+        launch_c64_to_c128(zj, rt, NRc, st);  // rt is free until the cycle ends
+        forward_f64(op, rt, work64, w, Rc, st);
+      } else {
+        apply_forward_tree(op, zj, wf, work, Rc, st);
+        launch_c64_to_c128(wf, w, NRc, st);
+      }
       double2 *hcol = gs.H + size_t(j) * (m + 1) * Rc;
       // classical Gram-Schmidt, applied twice
       launch_multidot(V, NRc, j + 1, w, n, Rc, partial, nblk, st);
@@ -294,9 +323,13 @@ static void solve_impl(const hodbf_op &op, int R, const void *b, int64_t ldb, vo
     // true residual r = b - Z x for every column of this cycle
     upload(colidx, act.data(), size_t(Ra) * 4);
     launch_gather_cols<double2>(xt, n, R, colidx, Ra, xc, st);
-    launch_c128_to_c64(xc, vf, n * Ra, st);
-    apply_forward_tree(op, vf, wf, work, Ra, st);
-    launch_c64_to_c128(wf, w, n * Ra, st);
+    if (Ra <= kF64Cols) {
+      forward_f64(op, xc, work64, w, Ra, st);
+    } else {
+      launch_c128_to_c64(xc, vf, n * Ra, st);
+      apply_forward_tree(op, vf, wf, work, Ra, st);
+      launch_c64_to_c128(wf, w, n * Ra, st);
+    }
     launch_gather_cols<double2>(bt, n, R, colidx, Ra, xc, st);
     launch_axpby(xc, w, w, n * Ra, st);
     launch_scatter_cols<double2>(w, n, Ra, colidx, R, rt, st);
@@ -309,6 +342,11 @@ static void solve_impl(const hodbf_op &op, int R, const void *b, int64_t ldb, vo
       const int q = act[size_t(k)];
       const double rr = std::sqrt(h[size_t(k)].x) / bnorm[size_t(q)];
       relres[size_t(q)] = rr;
+      // a cycle that met tol on its Arnoldi estimate but left the true residual just
+      // above it fell into the gap FP32 products open between the two: the column's next
+      // cycle aims at tol / 2, or it would stop again after a step or two that barely
+      // move the true residual
+      target[size_t(q)] = (rr > o.tol && rr <= 3 * o.tol) ? 0.5 : 1.0;
       if (!std::isfinite(rr)) {
         numeric_bad = true;
         active[size_t(q)] = 0;

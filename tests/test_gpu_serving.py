@@ -14,7 +14,7 @@ def test_alone_equals_in_mix():
     from paper_2111_01730_amd import serving
     from paper_2111_01730_amd.hodbf import P_FP32, Operator
     cases = [small_case(71, sides=(8, 8, 8), eps_range=(1.0, 12.0)),
-             small_case(72, sides=(8, 8, 8), eps_range=(1.0, 12.0)),
+             small_case(72, sides=(12, 12, 12), eps_range=(1.0, 12.0)),
              small_case(73, sides=(10, 9, 8), eps_range=(1.0, 12.0))]
     rng = np.random.default_rng(5)
     reqs = []
@@ -29,17 +29,31 @@ def test_alone_equals_in_mix():
     srv.close()
     assert all(r.converged for r in res), [(r.id, r.relres, r.iters) for r in res]
     assert max(r.batch_size for r in res) >= 2  # some requests shared a solve
+    smin = {}
     for r, q in zip(res, reqs):
         op = Operator(q.grid, **kw)
         b = op.plane_wave(q.dirs)
         x, info = op.solve(b, tol=1e-5)
         xa = x.cpu().numpy()
-        d = np.linalg.norm(r.x - xa, axis=0) / np.linalg.norm(xa, axis=0)
-        print(q.id, r.batch_size, r.iters, info["iters"], d, flush=True)
-        assert np.all(d <= 1e-3), (q.id, d)
-        # and the mixed result solves the exact system to the tolerance (+ compression)
         Z = vie.dense(q.grid)
         bn = b.cpu().numpy()
+        key = q.grid.n
+        if key not in smin:
+            sv = np.linalg.svd(Z, compute_uv=False)
+            smin[key] = (sv[-1], sv[0])
+        s_lo, s_hi = smin[key]
+        # two solutions whose residuals each meet tol differ by at most ||Z^-1|| times
+        # the sum of their residuals: 2 tol ||b|| as the solver measures them, plus the
+        # FP32 rounding of the products that measure them (2e-6 ||Z|| ||x||, 16 units of
+        # FP32 rounding); 1.5 covers the compressed operator (chi_con 1e-5) against Z
+        xn = np.linalg.norm(xa, axis=0)
+        d = np.linalg.norm(r.x - xa, axis=0) / xn
+        bound = 1.5 * (2 * 1e-5 * np.linalg.norm(bn, axis=0) + 2e-6 * s_hi * xn) / s_lo / xn
+        print(f"[request {q.id}: N {key}, batch {r.batch_size}, steps {r.iters} / {info['iters']}, "
+              f"alone vs mix {d.max():.2e} (bound {bound.min():.2e})]", flush=True)
+        assert np.all(d <= bound), (q.id, d, bound)
+        # and the mixed result solves the exact system to the tolerance (+ compression)
         rel = np.linalg.norm(Z @ r.x - bn, axis=0) / np.linalg.norm(bn, axis=0)
-        assert np.all(rel <= 1e-5 + 1e-3)
+        assert np.all(rel <= 1e-5 + 10 * 1e-5 * np.linalg.norm(Z, 2) *
+                      np.linalg.norm(r.x, axis=0) / np.linalg.norm(bn, axis=0))
         op.close()
