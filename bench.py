@@ -38,18 +38,15 @@ PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 PEAK_BF16_MFMA_TFLOPS = 2500.0
 # HBM bytes of one apply of this workload (R = 64) per kernel, from the FETCH_SIZE /
-# WRITE_SIZE counter runs recorded in profiles/*_traffic.md (scaled by a 256 MiB copy);
-# valid only while the kernel and packing sources hash to sources_sha256.  The
-# preconditioner's counters are not available: under --pmc the profiler crashes inside
-# the rocSOLVER factorisations of the preconditioner's construction; the same kernel on
-# the forward operator (profiles/grouped_mfma_s3_forward_c2_r64_traffic.md) moves the
-# same bytes as the FP32 kernel, 1.16x its algorithmic bytes.
-MEASURED_TRAFFIC = {"sources_sha256": "fd800eacd5218873512ff346d077dc865ebbbedcbe1ea35c9cc968d21953c03d",
-                    "precond_s3": {"bytes_per_apply": None, "launches_per_apply": 55},
-                    "forward_f32": {"bytes_per_apply": 1309388425.0 + 435899936.0,
+# WRITE_SIZE counter runs recorded in profiles/*_traffic.md (FETCH_SIZE scaled by what
+# it reads for a 256 MiB device copy, 131,083.5 KiB; WRITE_SIZE reads that copy as
+# 262,144 KiB); valid only while the kernel and packing sources hash to sources_sha256.
+MEASURED_TRAFFIC = {"sources_sha256": "189b6a0e73b6b871e55f5c316a9955663b659415f8f11ee0441f11cbee528684",
+                    "precond_s3": {"bytes_per_apply": 5490977272.4 + 1292105616.0,
+                                   "launches_per_apply": 41},
+                    "forward_f32": {"bytes_per_apply": 1312039988.2 + 438161904.0,
                                     "launches_per_apply": 10},
-                    "forward_s3": {"bytes_per_apply": 1309804968.2 + 435874192.0,
-                                   "launches_per_apply": 10}}
+                    "forward_s3": {"bytes_per_apply": None, "launches_per_apply": 10}}
 
 
 def measured_copy_gbs(nbytes=1 << 30, reps=10):
@@ -118,6 +115,15 @@ def sources_sha256():
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def precond_block_sums(op, R):
+    """Sum of m n and of (m + n) R over the stored preconditioner blocks (exported table):
+    the per-block factor and vector counts before any sharing of input rows."""
+    tab = op.export(3, np.int64).reshape(-1, 12)
+    m, n = tab[:, 8].astype(np.float64), tab[:, 9].astype(np.float64)
+    return {"sum_mn": float((m * n).sum()), "sum_m_plus_n_R": float(((m + n) * R).sum()),
+            "blocks": int(tab.shape[0])}
 
 
 def cpu_baseline_leg(seconds: float, workload: str) -> dict:
@@ -285,7 +291,9 @@ def solves_mode(args, cfg, Operator):
         _, info = op.solve(b, tol=TOL_SOL, use_precond="fp32_split")
     torch.cuda.synchronize()
     t = (time.perf_counter() - ts) / max(1, args.steps)
+    sums = precond_block_sums(op, int(b.shape[1]))
     print(json.dumps({"mode": "solves", "ms_per_solve": t * 1e3, "nrhs": int(b.shape[1]),
+                      "precond_blocks": sums,
                       "iters_max": int(info["iters"].max()),
                       "iters_mean": float(info["iters"].mean()),
                       "converged": bool(info["converged"].all())}), flush=True)
@@ -522,13 +530,14 @@ def main():
                        "precond_apply_ms": t_pre[c] * 1e3}
         log(f"[solve batched {c}] {variants[c]}")
 
-    # plain form: FP32 preconditioner, one column at a time
+    # plain form: FP32 preconditioner, one column at a time, every product with Z in FP32
     npl = min(args.plain_rhs, R)
     torch.cuda.synchronize()
     tp = time.perf_counter()
     plain_iters = []
     for q in range(npl):
-        _, pinfo = op.solve(b[:, q].contiguous(), tol=TOL_SOL, use_precond="fp32")
+        _, pinfo = op.solve(b[:, q].contiguous(), tol=TOL_SOL, use_precond="fp32",
+                            fp32_only=True)
         plain_iters.append(int(pinfo["iters"][0]))
     torch.cuda.synchronize()
     t_plain = (time.perf_counter() - tp) / npl
@@ -601,14 +610,7 @@ def main():
                     PEAK_BF16_MFMA_TFLOPS,
                     "k_grouped_mfma_s3 (preconditioner apply, FP32 factors on split-BF16 MFMA, "
                     "all launches)", "precond_s3")
-    if same_src:
-        fs = MEASURED_TRAFFIC["forward_s3"]
-        roof["traffic_note"] = (
-            "preconditioner counters unavailable (the profiler crashes inside the rocSOLVER "
-            "LU of its construction); the same kernel on the forward operator moves "
-            f"{fs['bytes_per_apply'] / fs['launches_per_apply']:.4e} bytes per launch, "
-            f"{fs['bytes_per_apply'] / (8.0 * st['entries_fwd'] + 8.0 * R * st['io_rows_fwd']):.2f}x "
-            "its algorithmic bytes")
+    roof["block_sums"] = precond_block_sums(op, R)
     copy_gbs = measured_copy_gbs()
     roof["measured_peaks"] = {"hbm_copy_gbs": copy_gbs}
     roof_fwd = roofline(st["entries_fwd"], st["io_rows_fwd"], st["fwd_stages"], t_fwd,

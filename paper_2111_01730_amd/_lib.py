@@ -35,7 +35,7 @@ class BuildParams(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("restart", C.c_int32), ("max_iter", C.c_int32),
-                ("use_precond", C.c_int32)]
+                ("use_precond", C.c_int32), ("fp32_only", C.c_int32)]
 
 
 class SolveInfo(C.Structure):

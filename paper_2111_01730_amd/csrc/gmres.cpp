@@ -112,6 +112,7 @@ static void solve_impl(const hodbf_op &op, int R, const void *b, int64_t ldb, vo
   const int64_t n = op.n;
   const int m = o.restart;
   const int pre_ft = precond_ftype(op, o.use_precond);
+  const int f64cols = o.fp32_only ? 0 : kF64Cols;
   const int64_t NR = n * R;
   const int nblk = multidot_blocks(n, R);
   const int64_t wrows = std::max(forward_work_rows(op), pre_ft >= 0 ? precond_work_rows(op) : 0);
@@ -245,7 +246,7 @@ static void solve_impl(const hodbf_op &op, int R, const void *b, int64_t ldb, vo
       launch_c128_to_c64(vj, vf, NRc, st);
       if (pre_ft >= 0) apply_precond_tree(op, pre_ft, vf, zj, work, Rc, st);
       else HIPCHK(hipMemcpyAsync(zj, vf, NRc * 8, hipMemcpyDeviceToDevice, st));
-      if (Rc <= kF64Cols) {
+      if (Rc <= f64cols) {
         launch_c64_to_c128(zj, rt, NRc, st);  // rt is free until the cycle ends
         forward_f64(op, rt, work64, w, Rc, st);
       } else {
@@ -323,7 +324,7 @@ static void solve_impl(const hodbf_op &op, int R, const void *b, int64_t ldb, vo
     // true residual r = b - Z x for every column of this cycle
     upload(colidx, act.data(), size_t(Ra) * 4);
     launch_gather_cols<double2>(xt, n, R, colidx, Ra, xc, st);
-    if (Ra <= kF64Cols) {
+    if (Ra <= f64cols) {
       forward_f64(op, xc, work64, w, Ra, st);
     } else {
       launch_c128_to_c64(xc, vf, n * Ra, st);
@@ -386,7 +387,8 @@ using namespace hodbf;
 static void check_solve_args(const hodbf_op *op, int32_t nrhs, const hodbf_solve_opts *opts) {
   if (!op || !opts) fail(HODBF_E_ARG, "NULL argument");
   if (nrhs < 0) fail(HODBF_E_ARG, "nrhs < 0");
-  if (!(opts->tol > 0) || opts->restart < 1 || opts->restart > 200 || opts->max_iter < 1)
+  if (!(opts->tol > 0) || opts->restart < 1 || opts->restart > 200 || opts->max_iter < 1 ||
+      (opts->fp32_only != 0 && opts->fp32_only != 1))
     fail(HODBF_E_ARG, "bad solve options");
 }
 

@@ -120,10 +120,11 @@ class Operator:
         return b.t()
 
     @staticmethod
-    def _solve_opts(tol, restart, max_iter, use_precond):
+    def _solve_opts(tol, restart, max_iter, use_precond, fp32_only=False):
         up = {"fp32": 8 + P_FP32, "bf16": 8 + P_BF16, "fp16": 8 + P_FP16,
               "fp32_split": 16 + P_FP32}.get(use_precond, use_precond)
-        return _lib.SolveOpts(tol=tol, restart=restart, max_iter=max_iter, use_precond=int(up))
+        return _lib.SolveOpts(tol=tol, restart=restart, max_iter=max_iter, use_precond=int(up),
+                              fp32_only=int(bool(fp32_only)))
 
     def solve_workspace(self, nrhs: int, restart=20, use_precond=1) -> int:
         """Device bytes the library allocates for one solve of nrhs columns (b, x and
@@ -133,17 +134,19 @@ class Operator:
         check(lib().hodbf_solve_workspace(self._h, int(nrhs), C.byref(opts), C.byref(n)))
         return n.value
 
-    def solve(self, b: torch.Tensor, tol=1e-4, restart=20, max_iter=3000, use_precond=1):
+    def solve(self, b: torch.Tensor, tol=1e-4, restart=20, max_iter=3000, use_precond=1,
+              fp32_only=False):
         """x ~ Z^{-1} b by right-preconditioned FGMRES; returns (x, info dict).
 
         use_precond: 0 none, 1 the operator's default copy, 'fp32', 'bf16' or 'fp16', or
-        'fp32_split' (the FP32 copy with split-BF16 arithmetic).
+        'fp32_split' (the FP32 copy with split-BF16 arithmetic).  fp32_only: every
+        product with Z in FP32 (no FP64 products for the last few columns).
         """
         if b.dtype != torch.complex128:
             raise ValueError("b must be complex128")
         bc, R = _as_cols(b, self.n)
         x = torch.empty_like(bc)
-        opts = self._solve_opts(tol, restart, max_iter, use_precond)
+        opts = self._solve_opts(tol, restart, max_iter, use_precond, fp32_only)
         iters = np.zeros(R, dtype=np.int32)
         conv = np.zeros(R, dtype=np.int32)
         rel = np.zeros(R, dtype=np.float64)

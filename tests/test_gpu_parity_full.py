@@ -97,10 +97,14 @@ def test_c2_precond_dense_bottom_full_size_matches_exported_factors(c2, which, s
 def test_c2_batched_mixed_solve_matches_exported_operator(c2):
     """The benchmarked solve (FP32 forward, split-BF16 preconditioner, FGMRES(20) to
     1e-4, 64 columns at once): re-applied by the oracle in FP64 with the exported
-    compressed operator, every column's residual is within 1.05 chi_sol plus the FP32
-    rounding bound of the library's own product (the solver's check runs in FP32 on x
-    rounded to FP32).  The residual with the exact (FFT) product is reported: it adds the
-    compression error, which on this ill-conditioned workload is not small against ||b||."""
+    compressed operator, every column's residual is within chi_sol plus the error of the
+    product the solver measured it with.  The solver's true residuals use the FP32
+    product of x, except for its last few columns (FP64 products); that FP32 product's
+    deviation from the FP64 one is measured here column by column (the library's
+    hodbf_apply on the same x against the oracle's re-application), so the slack is
+    this run's own, not a worst case.  The residual with the exact (FFT) product is
+    reported: it adds the compression error, which on this ill-conditioned workload is
+    not small against ||b||."""
     op, tol = c2["op"], c2["cfg"]["tol"]
     x, info = op.solve(c2["b"], tol=tol, use_precond="fp32_split")
     print(f"[c2 mixed solve: steps mean {info['iters'].mean():.1f} max {info['iters'].max()}, "
@@ -110,16 +114,15 @@ def test_c2_batched_mixed_solve_matches_exported_operator(c2):
     perm = c2["perm"]
     xt = x.cpu().numpy()[perm]
     bt = c2["bt"]
-    r = bt - c2["fwd"].apply_tree(xt)
+    zx64 = c2["fwd"].apply_tree(xt)
+    r = bt - zx64
     bn = np.linalg.norm(bt, axis=0)
     rel = np.linalg.norm(r, axis=0) / bn
-    dims = bounds.forward_stage_dims(c2["ftab"], c2["st"]["levels"])
-    # x enters the FP32 product rounded (u |x|) and the product's own rounding
-    g = bounds.worst_case_gamma(dims) + bounds.U32
-    slack = g * np.linalg.norm(bounds.absolute_hodbf(c2["fwd"]).apply_tree(np.abs(xt)), axis=0) / bn
-    print(f"[c2 mixed solve vs exported operator in FP64: relres max {rel.max():.3e}, "
-          f"bound {1.05 * tol:.2e} + rounding up to {slack.max():.2e}]", flush=True)
-    assert np.all(rel <= 1.05 * tol + slack), (rel.max(), slack.max())
+    zx32 = op.apply(x).cpu().numpy()[perm]
+    slack = np.linalg.norm(zx32 - zx64, axis=0) / bn
+    print(f"[c2 mixed solve vs exported operator in FP64: relres max {rel.max():.3e}; "
+          f"FP32 product vs FP64 up to {slack.max():.2e} of ||b||]", flush=True)
+    assert np.all(rel <= tol * (1 + 1e-6) + slack), (rel.max(), slack.max())
     g_ = c2["g"]
     xu = x.cpu().numpy()
     bu = c2["b"].cpu().numpy()

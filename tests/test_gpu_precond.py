@@ -120,6 +120,35 @@ def test_batched_solve_equals_single_column_solves(case):
         assert d <= 1e-3
 
 
+def test_fp64_tail_and_fp32_only_solves_agree(case):
+    # a batch of at most four columns runs its products with Z in FP64 by default; with
+    # fp32_only every product is FP32: both meet the tolerance against the dense operator
+    # and agree within what two solutions meeting it can differ by
+    import ctypes as C
+    from paper_2111_01730_amd import _lib
+    c, g, op, Z = case
+    b = op.plane_wave(c["dirs"][:3])
+    x64, i64 = op.solve(b, tol=1e-6, use_precond="fp32")
+    x32, i32 = op.solve(b, tol=1e-6, use_precond="fp32", fp32_only=True)
+    assert i64["converged"].all() and i32["converged"].all()
+    bn = b.cpu().numpy()
+    for x in (x64, x32):
+        xn = x.cpu().numpy()
+        rel = np.linalg.norm(Z @ xn - bn, axis=0) / np.linalg.norm(bn, axis=0)
+        assert np.all(rel <= 1e-6 + 1e-3), rel  # + the compression error of chi_con 1e-4
+    smin = np.linalg.svd(Z, compute_uv=False)[-1]
+    d = np.linalg.norm(x64.cpu().numpy() - x32.cpu().numpy(), axis=0)
+    bound = 2 * (1e-6 + 1e-5) * np.linalg.norm(bn, axis=0) / smin
+    print(f"[FP64 tail vs FP32 only: steps {i64['iters']} / {i32['iters']}, difference "
+          f"{d.max():.2e} (bound {bound.min():.2e})]", flush=True)
+    assert np.all(d <= bound)
+    opts = _lib.SolveOpts(tol=1e-6, restart=20, max_iter=10, use_precond=9, fp32_only=2)
+    xb = torch.empty_like(b)
+    code = _lib.lib().vie_solve(op._h, 3, C.c_void_p(b.t().contiguous().data_ptr()), op.n,
+                                C.c_void_p(xb.data_ptr()), op.n, C.byref(opts), None, None)
+    assert code == -1  # E_ARG
+
+
 def test_split_bf16_apply_is_reproducible_and_batch_independent(case):
     # every output element is owned by one work item and accumulated in a fixed chunk
     # order, so two calls agree bit for bit; a column alone runs the same arithmetic
