@@ -126,6 +126,39 @@ def precond_block_sums(op, R):
             "blocks": int(tab.shape[0])}
 
 
+def c3_forward(Operator, P_NONE, reps: int) -> dict:
+    """The forward apply of the 64^3 sphere (262,144 unknowns, 32 plane waves, chi_con
+    1e-4) on the tree-order entry, HIP events on the launch stream."""
+    import torch
+    from synth import config
+    cfg = config("c3_sphere_64")
+    t0 = time.perf_counter()
+    op = Operator(cfg["grid"], tol_con=cfg["tol"], seed=cfg["seed"])
+    build = time.perf_counter() - t0
+    st = op.stats()
+    b = op.plane_wave(cfg["dirs"])
+    perm = torch.as_tensor(op.perm().astype(np.int64), device="cuda")
+    xt = b[perm].to(torch.complex64).contiguous()
+    R = xt.shape[1]
+    for _ in range(2):
+        op.apply_tree(xt, 0)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        op.apply_tree(xt, 0)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / reps * 1e-3
+    fl = 8.0 * R * st["entries_fwd"]
+    out = {"n": op.n, "nrhs": R, "build_s": build, "entries_fwd": st["entries_fwd"],
+           "apply_ms": t * 1e3, "apply_gflops": fl / t / 1e9,
+           "mfma_frac": fl / t / 1e12 / PEAK_FP32_MFMA_TFLOPS}
+    op.close()
+    return out
+
+
 def cpu_baseline_leg(seconds: float, workload: str) -> dict:
     """The oracle timed on the host over a bounded sample of the workload: its own
     FGMRES(20) (complex FP64, no preconditioner: the oracle's multiplicative inverse is a
@@ -422,6 +455,7 @@ def main():
     ap.add_argument("--variant-max-iter", type=int, default=300)
     ap.add_argument("--plain-rhs", type=int, default=4, help="columns timed in the plain form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c3", action="store_true", help="skip the 64^3 forward apply")
     ap.add_argument("--cpu-baseline-leg", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--apply-reps", type=int, default=20)
     ap.add_argument("--apply-nrhs", type=int, default=0,
@@ -618,6 +652,14 @@ def main():
                         "forward_f32")
     roof_fwd["per_stage"] = stage_roofline(op, st, R, t_fwd)
     roof_fwd["mfma_frac"] = flops_fwd / t_fwd / 1e12 / PEAK_FP32_MFMA_TFLOPS
+    # the 64^3 sphere's forward apply (its preconditioner is beyond these minutes): the
+    # apply GFLOP/s half of the metric on the larger configuration
+    c3 = None
+    if not args.no_c3:
+        del op
+        torch.cuda.empty_cache()
+        c3 = c3_forward(Operator, P_NONE, args.apply_reps)
+        log(f"[c3 forward] {c3}")
     out = {
         "metric": "HOD-BF apply GFLOP/s + solves/sec at 1e-4 rel. residual, mixed vs plain FP32",
         "value": solves_per_s,
@@ -657,6 +699,7 @@ def main():
         "roofline_forward": roof_fwd,
         "cpu_baseline": cpu,
         "cpu_baseline_1core": cpu_1core,
+        "c3_sphere_64_forward": c3,
     }
     print(json.dumps(out), flush=True)
     return 0
