@@ -136,9 +136,10 @@ hodbf_status hodbf_apply_noalloc(const hodbf_op *op, int32_t nrhs, hodbf_dtype d
                                  const void *x, int64_t ldx, void *y, int64_t ldy, void *stream);
 
 /*
- * hodbf_precond_apply -- y = P x with P ~ Z^{-1}: the leaf inverses D_tau^{-1}
- * followed, level by level towards the root, by z(tau) <- (I + X_tau) z(tau)
- * (Algorithm 1 unrolled).  Uses the default arithmetic: the FP32 copy with split-BF16
+ * hodbf_precond_apply -- y = P x with P ~ Z^{-1}: the dense inverses D_tau^{-1} of the
+ * recursion's leaves (the tree's leaves, or the level L_H - d nodes with
+ * precond_dense_levels = d) followed, level by level towards the root, by
+ * z(tau) <- (I + X_tau) z(tau) (Algorithm 1 unrolled).  Uses the default arithmetic: the FP32 copy with split-BF16
  * products (see hodbf_apply_tree, which 6) if the FP32 copy is stored, else the FP16
  * copy, else the BF16 copy.  FP32 accumulation.  E_STATE if built without one.
  */
