@@ -272,16 +272,19 @@ std::vector<cd> lstsq(std::vector<cd> A, int m, int n, std::vector<cd> B, int nr
   if (m == 0 || n == 0 || nrhs == 0) return X;
   std::vector<int> piv(n);
   for (int c = 0; c < n; ++c) piv[c] = c;
-  std::vector<double> cn(n);
+  // trailing column norms, downdated by each new row of R and recomputed once one has
+  // fallen below 5% of its last computed value
+  std::vector<double> cn(n), cn0(n);
   for (int c = 0; c < n; ++c) {
     double s = 0;
-    for (int i = 0; i < m; ++i) s += std::norm(A[size_t(c) * m + i]);
-    cn[c] = s;
+    const double *col = reinterpret_cast<const double *>(A.data() + size_t(c) * m);
+    for (int i = 0; i < 2 * m; ++i) s += col[i] * col[i];
+    cn[c] = cn0[c] = s;
   }
   const int kmax = std::min(m, n);
   int r = 0;
   double top = 0;
-  std::vector<cd> u(m);
+  std::vector<double> u(2 * size_t(m));
   for (int j = 0; j < kmax; ++j) {
     int p = j;
     for (int c = j + 1; c < n; ++c)
@@ -289,36 +292,51 @@ std::vector<cd> lstsq(std::vector<cd> A, int m, int n, std::vector<cd> B, int nr
     if (p != j) {
       std::swap_ranges(A.begin() + size_t(j) * m, A.begin() + size_t(j) * m + m, A.begin() + size_t(p) * m);
       std::swap(cn[j], cn[p]);
+      std::swap(cn0[j], cn0[p]);
       std::swap(piv[j], piv[p]);
     }
-    cd *x = A.data() + size_t(j) * m;
+    double *x = reinterpret_cast<double *>(A.data() + size_t(j) * m);
     double xn2 = 0;
-    for (int i = j; i < m; ++i) xn2 += std::norm(x[i]);
+    for (int i = 2 * j; i < 2 * m; ++i) xn2 += x[i] * x[i];
     const double xn = std::sqrt(xn2);
     if (j == 0) top = xn;
     if (!(xn > 1e-13 * top)) break;
-    const double aa = std::abs(x[j]);
-    const cd phase = aa > 0 ? x[j] / aa : cd(1.0, 0.0);
-    const cd beta = -phase * xn;
+    const double aa = std::hypot(x[2 * j], x[2 * j + 1]);
+    const double pr = aa > 0 ? x[2 * j] / aa : 1.0, pi = aa > 0 ? x[2 * j + 1] / aa : 0.0;
+    const double br = -pr * xn, bi = -pi * xn;  // the reflector maps x(j:m) to beta e_1
     const int len = m - j;
-    for (int i = 0; i < len; ++i) u[i] = x[j + i];
-    u[0] -= beta;
-    const double uu = 2.0 * xn * (xn + aa);
-    auto reflect = [&](cd *col) {
-      cd s = 0;
-      for (int i = 0; i < len; ++i) s += std::conj(u[i]) * col[j + i];
-      s *= 2.0 / uu;
-      for (int i = 0; i < len; ++i) col[j + i] -= u[i] * s;
+    for (int i = 0; i < 2 * len; ++i) u[i] = x[2 * j + i];
+    u[0] -= br;
+    u[1] -= bi;
+    const double f = 2.0 / (2.0 * xn * (xn + aa));  // 2 / u^H u
+    auto reflect = [&](cd *column) {
+      double *col = reinterpret_cast<double *>(column) + 2 * j;
+      double sr = 0, si = 0;  // u^H col
+      for (int i = 0; i < len; ++i) {
+        sr += u[2 * i] * col[2 * i] + u[2 * i + 1] * col[2 * i + 1];
+        si += u[2 * i] * col[2 * i + 1] - u[2 * i + 1] * col[2 * i];
+      }
+      sr *= f;
+      si *= f;
+      for (int i = 0; i < len; ++i) {
+        col[2 * i] -= u[2 * i] * sr - u[2 * i + 1] * si;
+        col[2 * i + 1] -= u[2 * i] * si + u[2 * i + 1] * sr;
+      }
+      return col;
     };
-    for (int c = j + 1; c < n; ++c) reflect(A.data() + size_t(c) * m);
-    for (int c = 0; c < nrhs; ++c) reflect(B.data() + size_t(c) * m);
-    x[j] = beta;
-    for (int i = j + 1; i < m; ++i) x[i] = 0;
     for (int c = j + 1; c < n; ++c) {
-      double s = 0;
-      for (int i = j + 1; i < m; ++i) s += std::norm(A[size_t(c) * m + i]);
-      cn[c] = s;
+      const double *col = reflect(A.data() + size_t(c) * m);
+      cn[c] -= col[0] * col[0] + col[1] * col[1];
+      if (cn[c] <= 0.05 * cn0[c]) {
+        double s2 = 0;
+        for (int i = 2; i < 2 * len; ++i) s2 += col[i] * col[i];
+        cn[c] = cn0[c] = s2;
+      }
     }
+    for (int c = 0; c < nrhs; ++c) reflect(B.data() + size_t(c) * m);
+    x[2 * j] = br;
+    x[2 * j + 1] = bi;
+    for (int i = 2 * (j + 1); i < 2 * m; ++i) x[i] = 0;
     r = j + 1;
   }
   std::vector<cd> t(r);
