@@ -97,24 +97,27 @@ __global__ __launch_bounds__(kBlock) void k_gather_rows(const double2 *__restric
 
 // ---------------------------------------------------------------------------
 // Grouped complex GEMM in FP64 over the descriptors of the applies (device.h): one
-// workgroup per (tile, slice of kQ right-hand sides); a tile's output rows (at most
+// workgroup per (tile, slice of Q right-hand sides); a tile's output rows (at most
 // kTileRows) are the sum over its pairs of the FP32-stored factor block (times the
 // pair's scale) and its input rows, accumulated in FP64; rows are scattered through the
 // tile's row map (beta 0 stores, beta 1 adds: every output element has one owner).
-// Factor and input chunks of kK columns pass through LDS.
-constexpr int kQ = 32;  // right-hand sides per workgroup
+// Factor and input chunks of kK columns pass through LDS.  Q = 32 for wide
+// multi-vectors (the construction), Q = 8 for at most 8 columns (the solver's last
+// columns), so narrow products do not pay for 32.
 constexpr int kK = 16;  // inner-dimension chunk
-constexpr int kPerThread = kTileRows * kQ / kBlock;  // outputs per thread (8)
 
+template <int Q>
 __global__ __launch_bounds__(kBlock) void k_grouped_f64(
     const Seg *__restrict__ segs, const Pair *__restrict__ pairs, const RowMap *__restrict__ rowmap,
     const float2 *__restrict__ F, const double2 *__restrict__ X, const double2 *__restrict__ T,
     double2 *__restrict__ OUT, int R, int beta, int nsl) {
+  constexpr int kPerThread = kTileRows * Q / kBlock;  // outputs per thread (8 or 2)
+  static_assert(kPerThread * kBlock == kTileRows * Q, "tile not divisible");
   __shared__ double2 As[kK][kTileRows];
-  __shared__ double2 Xs[kK][kQ];
+  __shared__ double2 Xs[kK][Q];
   const int tid = threadIdx.x;
   const int seg = blockIdx.x / nsl;
-  const int q0 = (blockIdx.x % nsl) * kQ;
+  const int q0 = (blockIdx.x % nsl) * Q;
   const Seg sg = segs[seg];
   const int row = tid % kTileRows;   // output row of this thread
   const int qg = tid / kTileRows;    // its group of kPerThread columns
@@ -135,9 +138,9 @@ __global__ __launch_bounds__(kBlock) void k_grouped_f64(
         }
         As[kk][i] = a;
       }
-      // input chunk: kK rows of the pair's input, kQ columns
-      for (int e = tid; e < kK * kQ; e += kBlock) {
-        const int kk = e / kQ, q = e % kQ;
+      // input chunk: kK rows of the pair's input, Q columns
+      for (int e = tid; e < kK * Q; e += kBlock) {
+        const int kk = e / Q, q = e % Q;
         double2 v = make_double2(0.0, 0.0);
         if (k0 + kk < pr.n && q0 + q < R) v = in[int64_t(pr.in_row + k0 + kk) * R + q0 + q];
         Xs[kk][q] = v;
@@ -210,11 +213,16 @@ void launch_grouped_f64(const Seg *segs, const Pair *pairs, const RowMap *rowmap
                         int64_t ns, const float2 *F, const double2 *X, const double2 *T,
                         double2 *OUT, int R, int beta, hipStream_t st) {
   if (ns <= 0 || R <= 0) return;
-  const int nsl = (R + kQ - 1) / kQ;
+  const int q = R <= 8 ? 8 : 32;
+  const int nsl = (R + q - 1) / q;
   const int64_t items = ns * nsl;
   if (items > (int64_t(1) << 31) - 1) fail(HODBF_E_ARG, "construction launch too large");
-  hipLaunchKernelGGL(k_grouped_f64, dim3(unsigned(items)), dim3(kBlock), 0, st, segs + s0, pairs,
-                     rowmap, F, X, T, OUT, R, beta, nsl);
+  if (q == 8)
+    hipLaunchKernelGGL(k_grouped_f64<8>, dim3(unsigned(items)), dim3(kBlock), 0, st, segs + s0,
+                       pairs, rowmap, F, X, T, OUT, R, beta, nsl);
+  else
+    hipLaunchKernelGGL(k_grouped_f64<32>, dim3(unsigned(items)), dim3(kBlock), 0, st, segs + s0,
+                       pairs, rowmap, F, X, T, OUT, R, beta, nsl);
 }
 
 }  // namespace hodbf
