@@ -130,6 +130,9 @@ extern "C" hodbf_status hodbf_precond_probe(const hodbf_build_params *params, in
                                double(params->leaf_size), double(params->seed),
                                double(params->precond_min_level),
                                double(params->precond_dense_levels)};
+    // the intermediate tolerance's override is part of what was built
+    const char *inner_env = std::getenv("HODBF_CHI_INNER");
+    key.push_back(inner_env ? std::atof(inner_env) : -1.0);
     if (params->eps_r && n > 0) key.insert(key.end(), params->eps_r, params->eps_r + 2 * n);
     if (key != g_pp_key) {
       if (!(params->tol_fact > 0 && params->tol_fact < 1)) fail(HODBF_E_ARG, "tol_fact must lie in (0, 1)");
