@@ -170,7 +170,7 @@ typedef struct {
   int32_t use_precond;  /* 0: none; 1: operator default; 8 + HODBF_P_FP32 / _BF16 / _FP16;
                            16 + HODBF_P_FP32: the FP32 copy with split-BF16 arithmetic
                            (see hodbf_apply_tree, which 6) */
-  int32_t fp32_only;    /* 0 (default): once at most 4 columns are still iterating, their
+  int32_t fp32_only;    /* 0 (default): once at most 16 columns are still iterating, their
                            products with Z (Arnoldi steps and true residuals) run in FP64
                            arithmetic over the FP32-stored factors; 1: every product in
                            FP32 as hodbf_apply */

@@ -102,8 +102,8 @@ __global__ __launch_bounds__(kBlock) void k_gather_rows(const double2 *__restric
 // pair's scale) and its input rows, accumulated in FP64; rows are scattered through the
 // tile's row map (beta 0 stores, beta 1 adds: every output element has one owner).
 // Factor and input chunks of kK columns pass through LDS.  Q = 32 for wide
-// multi-vectors (the construction), Q = 8 for at most 8 columns (the solver's last
-// columns), so narrow products do not pay for 32.
+// multi-vectors (the construction), 16 or 8 for at most 16 or 8 columns (the solver's
+// last columns), so narrow products do not pay for 32.
 constexpr int kK = 16;  // inner-dimension chunk
 
 template <int Q>
@@ -213,12 +213,15 @@ void launch_grouped_f64(const Seg *segs, const Pair *pairs, const RowMap *rowmap
                         int64_t ns, const float2 *F, const double2 *X, const double2 *T,
                         double2 *OUT, int R, int beta, hipStream_t st) {
   if (ns <= 0 || R <= 0) return;
-  const int q = R <= 8 ? 8 : 32;
+  const int q = R <= 8 ? 8 : (R <= 16 ? 16 : 32);
   const int nsl = (R + q - 1) / q;
   const int64_t items = ns * nsl;
   if (items > (int64_t(1) << 31) - 1) fail(HODBF_E_ARG, "construction launch too large");
   if (q == 8)
     hipLaunchKernelGGL(k_grouped_f64<8>, dim3(unsigned(items)), dim3(kBlock), 0, st, segs + s0,
+                       pairs, rowmap, F, X, T, OUT, R, beta, nsl);
+  else if (q == 16)
+    hipLaunchKernelGGL(k_grouped_f64<16>, dim3(unsigned(items)), dim3(kBlock), 0, st, segs + s0,
                        pairs, rowmap, F, X, T, OUT, R, beta, nsl);
   else
     hipLaunchKernelGGL(k_grouped_f64<32>, dim3(unsigned(items)), dim3(kBlock), 0, st, segs + s0,

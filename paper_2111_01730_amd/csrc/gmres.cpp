@@ -56,13 +56,13 @@ static int precond_ftype(const hodbf_op &op, int use_precond) {
   fail(HODBF_E_ARG, "unknown use_precond");
 }
 
-// The last few columns of a solve (at most kF64Cols still iterating) run their products
+// The last columns of a solve (at most kF64Cols still iterating) run their products
 // with Z in FP64 arithmetic over the FP32-stored factors, inside the Arnoldi process and
 // for the true residual.  Products that round their input and accumulate in FP32 err by
 // about u32 ||Z|| ||z||; for a column whose Krylov vectors reach the ill-conditioned
 // directions that P amplifies, that error approaches the residual still to be removed,
 // and the column stalls just above tol, each restart undoing what the last one gained.
-constexpr int kF64Cols = 4;
+constexpr int kF64Cols = 16;
 
 // y = Z_con x in FP64 (x, y tree order, R columns interleaved; T: stage workspace)
 static void forward_f64(const hodbf_op &op, const double2 *x, double2 *T, double2 *y, int R,
